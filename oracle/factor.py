@@ -1,0 +1,117 @@
+"""The range-separated correlation factor and the kernels k_i (oracle).
+
+Test infrastructure only.
+
+Eq. (rs12):  f(r) = (1 + r/2) exp(-mu r^2) + S_n(mu r^2) c0 r^rho exp(B r)
+Eq. (ttdamp): S_n(x) = 1 - exp(-x) sum_{k<=n} x^k / k!
+Kernels, Eqs. (k1)-(k6): k1 = 1/r, k2 = f/r, k3 = f, k4 = f f', k6 = f_r f'_r
+where f_r = df/dr (Eq. (I6_) and the double-commutator identity above it).
+
+Everything is evaluated pointwise in double-double on arrays of r > 0.
+The oracle integrates K_i(r) = r k_i(r), the combination that appears in
+the one-dimensional representation Eq. (bfinal).
+"""
+from dataclasses import dataclass
+import math
+import numpy as np
+from . import dd
+
+
+@dataclass(frozen=True)
+class Factor:
+    """Parameters (c0, rho, B, mu, n) of Eq. (rs12)/(ttdamp)."""
+    c0: float
+    rho: float
+    B: float
+    mu: float
+    n: int = 0
+
+
+def tang_toennies(n, x):
+    """S_n(x) of Eq. (ttdamp) in DD for DD x >= 0.
+
+    For x < 2 the tail form exp(-x) sum_{k>n} x^k/k! avoids the cancellation
+    of 1 - exp(-x)(...) (the two expressions are identical).
+    """
+    x = dd.DD(x)
+    ex = dd.exp(-x)
+    # head: sum_{k<=n} x^k/k!
+    term = dd.ones(x.shape)
+    head = dd.ones(x.shape)
+    for k in range(1, n + 1):
+        term = term * x / float(k)
+        head = head + term
+    big = 1.0 - ex * head
+    small_mask = x.hi < 0.5
+    if not np.any(small_mask):
+        return big
+    # tail: sum_{k>n} x^k/k!, 28 terms give < 1e-34 relative for x < 0.5
+    xs = dd.where(small_mask, x, 0.0)
+    t = dd.ones(x.shape)
+    for k in range(1, n + 1):
+        t = t * xs / float(k)
+    tail = dd.zeros(x.shape)
+    for k in range(n + 1, n + 29):
+        t = t * xs / float(k)
+        tail = tail + t
+    small = ex * tail
+    return dd.where(small_mask, small, big)
+
+
+def f_value(fac, r):
+    """f(r) of Eq. (rs12) in DD."""
+    r = dd.DD(r)
+    mr2 = fac.mu * r * r
+    g = dd.exp(-mr2)
+    short = (1.0 + 0.5 * r) * g
+    if fac.c0 == 0.0:
+        return short
+    lr = dd.exp(dd.log(r) * fac.rho + r * fac.B)
+    return short + tang_toennies(fac.n, mr2) * lr * fac.c0
+
+
+def f_deriv(fac, r):
+    """df/dr of Eq. (rs12) in DD.
+
+    d/dr[(1 + r/2) e^{-mu r^2}] = (1/2 - 2 mu r - mu r^2) e^{-mu r^2};
+    dS_n(x)/dx = e^{-x} x^n / n!, so d/dr S_n(mu r^2) = 2 mu r e^{-mu r^2}
+    (mu r^2)^n / n!; and d/dr[r^rho e^{B r}] = (rho/r + B) r^rho e^{B r}.
+    """
+    r = dd.DD(r)
+    mr2 = fac.mu * r * r
+    g = dd.exp(-mr2)
+    short = (0.5 - 2.0 * fac.mu * r - fac.mu * r * r) * g
+    if fac.c0 == 0.0:
+        return short
+    lr = dd.exp(dd.log(r) * fac.rho + r * fac.B)
+    dS = 2.0 * fac.mu * r * g * dd.ipow(mr2, fac.n) / float(math.factorial(fac.n))
+    S = tang_toennies(fac.n, mr2)
+    return short + fac.c0 * lr * (dS + S * (fac.rho / r + fac.B))
+
+
+def kernel_times_r(cls, fac, facp, r):
+    """K_i(r) = r k_i(r) for class i in {1,2,3,4,6} (DD)."""
+    r = dd.DD(r)
+    if cls == 1:
+        return dd.ones(r.shape)
+    if cls == 2:
+        return f_value(fac, r)
+    if cls == 3:
+        return r * f_value(fac, r)
+    if cls == 4:
+        return r * f_value(fac, r) * f_value(facp, r)
+    if cls == 6:
+        return r * f_deriv(fac, r) * f_deriv(facp, r)
+    raise ValueError(f"class {cls} has no kernel of its own (I5 is built from I3)")
+
+
+def growth_rate(cls, fac, facp):
+    """Largest exponential growth rate b of K_i (used to place quadrature panels)."""
+    b = 0.0
+    if cls in (2, 3):
+        b = max(fac.B, 0.0) if fac.c0 != 0 else 0.0
+    elif cls in (4, 6):
+        b1 = max(fac.B, 0.0) if fac.c0 != 0 else 0.0
+        b2 = max(facp.B, 0.0) if facp.c0 != 0 else 0.0
+        b = b1 + b2
+    return b
