@@ -1,0 +1,182 @@
+/*
+ * f12int.h - C ABI of the MI355X (gfx950) library that evaluates, in batches,
+ * the two-electron integral classes of explicitly correlated (F12) methods
+ * with the range-separated correlation factor of Silkowski, Lesiuk and
+ * Moszynski (arXiv:1412.5070), over contracted Cartesian Gaussian shells.
+ *
+ *   I1 = (ab| 1/r12 |cd)            Eq. (I1)
+ *   I2 = (ab| f/r12 |cd)            Eq. (I2)
+ *   I3 = (ab| f |cd)                Eq. (I3)
+ *   I4 = (ab| f f' |cd)             Eq. (I4)
+ *   I5 = (ab| [f, T1] |cd)          Eq. (I5), evaluated as 1/2 (lap_A - lap_B) I3, Eq. (I5_)
+ *   I6 = (ab| [[f, T1], f'] |cd)    Eq. (I6), evaluated as (ab| f_r f'_r |cd), Eq. (I6_)
+ *
+ * with f(r) = (1 + r/2) exp(-mu r^2) + S_n(mu r^2) c0 r^rho exp(B r)   Eq. (rs12)
+ * and  S_n(x) = 1 - exp(-x) sum_{k<=n} x^k / k!                        Eq. (ttdamp).
+ *
+ * Orbitals are unnormalised primitive Cartesian Gaussians x_A^i y_A^k z_A^m
+ * exp(-a r_A^2) (Eq. (basis)); contraction coefficients are used as given.
+ * Cartesian components of a shell of angular momentum l are ordered (i,k,m)
+ * with i from l down to 0, then k from l-i down to 0.  Coordinates in bohr.
+ *
+ * Conventions for every function:
+ *  - return an int status: F12_OK (0) or a negative f12_status; nothing is
+ *    thrown across the ABI.  Argument validation happens before any launch.
+ *  - host pointers are read during the call only (the library copies what it
+ *    keeps); device pointers ("d_") must stay valid until the work enqueued
+ *    on the given HIP stream has completed.
+ *  - handles are owned by the library and freed by the matching *_destroy.
+ *  - stream arguments are hipStream_t passed as void* (NULL = default stream).
+ */
+#ifndef F12INT_H
+#define F12INT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  F12_OK = 0,
+  F12_EINVAL = -1,    /* bad argument (null pointer, out-of-range index, ...)   */
+  F12_EPARAM = -2,    /* factor parameters rejected (mu <= 0, non-finite, n   */
+                      /* violating n > -rho/2 - 1 for rho < -2, or a negative   */
+                      /* integer power in the kernel: not supported)           */
+  F12_ELMAX = -3,     /* angular momentum above the supported maximum           */
+  F12_ENOMEM = -4,    /* host or device allocation failed                       */
+  F12_EDEVICE = -5,   /* a HIP runtime call failed                              */
+  F12_EBUFSIZE = -6   /* output buffer too small for the requested range        */
+} f12_status;
+
+typedef enum {
+  F12_I1_COULOMB = 1,
+  F12_I2_F_OVER_R = 2,
+  F12_I3_F = 3,
+  F12_I4_FFP = 4,
+  F12_I5_COMM_T1 = 5,
+  F12_I6_DF_DFP = 6
+} f12_class;
+
+/* Parameters of one range-separated factor, Eq. (rs12) and Eq. (ttdamp).
+ * c0, rho, B: any finite reals; mu > 0; n >= 0 integer, and n > -rho/2 - 1
+ * when rho < -2 (the paper's condition for a regular factor at r = 0). */
+typedef struct {
+  double c0, rho, B, mu;
+  int32_t n;
+  int32_t reserved; /* must be 0 */
+} f12_factor;
+
+/* One contracted shell: angular momentum l (0..F12_LMAX), nprim primitives
+ * whose exponents/coefficients are exps/coefs[first_prim .. first_prim+nprim),
+ * centred on centre index `center`. */
+typedef struct {
+  int32_t l, nprim, center, first_prim;
+} f12_shell;
+
+#define F12_LMAX 3         /* s, p, d, f shells                                  */
+#define F12_MAX_KPRIM 16   /* primitives per shell                               */
+
+typedef struct f12_basis f12_basis;
+typedef struct f12_pairs f12_pairs;
+typedef struct f12_kernel f12_kernel;
+typedef struct f12_quartets f12_quartets;
+
+/* ---------------------------------------------------------------- basis ---- */
+/* Copies the geometry and shells.  xyz: ncenter*3 doubles; shells: nshell
+ * entries; exps/coefs: nprim_total doubles each (exponents > 0). */
+int f12_basis_create(int32_t ncenter, const double *xyz, int32_t nshell,
+                     const f12_shell *shells, int32_t nprim_total,
+                     const double *exps, const double *coefs, f12_basis **out);
+void f12_basis_destroy(f12_basis *basis);
+
+/* ---------------------------------------------------------------- pairs ---- */
+/* Shell-pair and primitive-pair data on the device (McMurchie-Davidson
+ * Gaussian product, Sec. II.B: p = a + b, P = (aA + bB)/p, c_a c_b).
+ * ordered = 0: pairs (i, j) with i >= j (for f12_quartets_build);
+ * ordered = 1: all pairs (i, j) (for explicit quartet lists).
+ * Pair index of (i, j): ordered ? i*nshell + j : i*(i+1)/2 + j.
+ * The kernels are enqueued on `stream`; the call returns after they finish. */
+int f12_pairs_build(const f12_basis *basis, int32_t ordered, void *stream, f12_pairs **out);
+int f12_pairs_count(const f12_pairs *pairs, int64_t *n_shell_pairs, int64_t *n_prim_pairs);
+void f12_pairs_destroy(f12_pairs *pairs);
+
+/* -------------------------------------------------------------- kernel ---- */
+/* Kernel function k_i for class `cls` with factors f and fp (fp may be NULL,
+ * meaning fp = f; only I4 and I6 use fp).  Builds the term table of
+ * r*k_i(r) = sum_t c_t r^alpha_t exp(b_t r - g_t r^2) by expanding
+ * Eq. (rs12)/(ttdamp) (and d/dr of it for I6), groups the terms into chains of
+ * equal (b, g, alpha mod 1), and builds the auxiliary-function tables
+ * W_a(x) = R int_0^inf t^a exp(-(t-x)^2) dt (Eq. (sila) with gamma = 1) for the
+ * chains' alpha families; uploads everything to the current device. */
+int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_factor *fp, f12_kernel **out);
+/* Copies up to `cap` terms as (c, alpha, b, g) quadruples into out[4*k..]. */
+int f12_kernel_terms(const f12_kernel *k, int32_t *nterms, double *out, int32_t cap);
+void f12_kernel_destroy(f12_kernel *k);
+
+/* ------------------------------------------------------------ quartets ---- */
+/* All unique quartets of class `cls` over bra and ket pairs built from the
+ * same basis with unordered pair sets (ordered = 0): for I1-I4 and I6 the
+ * bra pair index >= the ket pair index (8-fold symmetry); for I5 every
+ * (bra, ket) combination (no bra-ket symmetry; (ba|cd) = -(ab|cd) and
+ * (ab|dc) = (ab|cd) give the remaining blocks).
+ * If screen_tol > 0 a quartet is kept when Q_ab Q_cd >= screen_tol with
+ * Q_ab = sqrt(max |(ab|k|ab)|) evaluated with `screen_kernel` (use an I3
+ * kernel for I5); screen_kernel may be NULL when screen_tol <= 0.
+ * The public order (offsets, output, f12_quartet_list) groups the quartets
+ * by (l_a, l_b, l_c, l_d) and keeps the enumeration order inside a group. */
+int f12_quartets_build(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
+                       double screen_tol, const f12_kernel *screen_kernel, void *stream,
+                       f12_quartets **out, int64_t *n_quartets, int64_t *n_out_doubles);
+/* An explicit list of nq shell quadruples (a, b, c, d) (host int32[4*nq]);
+ * bra and ket must be ordered pair sets.  The public order groups the list
+ * by (l_a, l_b, l_c, l_d) (stable): read it back with f12_quartet_list. */
+int f12_quartets_from_list(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
+                           const int32_t *shell_quads, int64_t nq, f12_quartets **out,
+                           int64_t *n_out_doubles);
+/* offsets: host int64[n_quartets + 1]; block q occupies
+ * [offsets[q], offsets[q+1]) doubles, row-major [a][b][c][d]. */
+int f12_quartet_offsets(const f12_quartets *q, int64_t *offsets);
+/* shell_quads: host int32[4 * n_quartets] in public order. */
+int f12_quartet_list(const f12_quartets *q, int32_t *shell_quads);
+/* Number of primitive quartets in the list (work measure). */
+int f12_quartets_prim_count(const f12_quartets *q, int64_t *n_prim_quartets);
+void f12_quartets_destroy(f12_quartets *q);
+
+/* ---------------------------------------------------------------- eval ---- */
+/* Enqueues on `stream` the evaluation of quartets [q_begin, q_end) (public
+ * order) with kernel `k` (its class must match the list's).  Block q is
+ * written to d_out + offsets[q] - offsets[q_begin]; out_capacity is the
+ * number of doubles available at d_out.  Asynchronous: returns after the
+ * launches; device-side problems are reported by f12_stream_status.
+ * Scratch memory is owned by the quartet list (one eval at a time per list). */
+int f12_eval(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
+             double *d_out, int64_t out_capacity, void *stream);
+
+/* ------------------------------------------------------------ diagnostics -- */
+/* Radial derivatives A_n = (R^-1 d/dR)^n B_i (Eq. (bfinal), n = 0..L) of the
+ * kernel's basic integral, computed by the same device code as f12_eval,
+ * for n primitive quartets given by exponent sums p, q and distance R.
+ * d_p, d_q, d_R: device double[n]; d_A: device double[(L+1) n] with A_k of
+ * point i at d_A[k*n + i].  route: 0 = the switch f12_eval uses (small-T
+ * series below T = xi R^2 = 2.5 / 4.5 / 6 for L <= 4 / <= 8 / > 8, the
+ * large-T lowering route above);
+ * 1 = small-T series; 2 = large-T route with the exp(-xi (r+R)^2) side kept.
+ * Asynchronous on `stream`. */
+int f12_aux_radial(const f12_kernel *k, int64_t n, const double *d_p, const double *d_q,
+                   const double *d_R, int32_t L, int32_t route, double *d_A, void *stream);
+/* Host-side table builder: W_a(x) = R int_0^inf t^a exp(-(t-x)^2) dt
+ * (Eq. (sila) with beta = 2x, gamma = 1, times exp(-x^2)) for
+ * a = alpha0 + m, m = m_lo..m_hi (alpha0 in [0,1); is_int = 1 for alpha0 = 0
+ * requires m_lo >= 0).  out: host double[m_hi - m_lo + 1]. */
+int f12_aux_w_column(double alpha0, int32_t is_int, int32_t m_lo, int32_t m_hi, double x,
+                     double *out);
+
+/* Synchronises `stream` and reports a HIP error if one occurred. */
+int f12_stream_status(void *stream);
+const char *f12_strerror(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* F12INT_H */

@@ -1,0 +1,964 @@
+// Host side of the library: C ABI, term tables of the kernels k_i, the
+// auxiliary-function tables, shell pairs, quartet lists and evaluation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "../../include/f12int.h"
+#include "f12_dd.h"
+#include "f12_internal.h"
+#include "f12_launch.h"
+
+using namespace f12;
+
+// ============================================================================
+// helpers
+// ============================================================================
+namespace {
+
+template <typename T>
+struct DevBuf {
+  T *ptr = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    n = 0;
+  }
+  bool alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    if (hipMalloc((void **)&ptr, count * sizeof(T)) != hipSuccess) {
+      ptr = nullptr;
+      return false;
+    }
+    n = count;
+    return true;
+  }
+  bool upload(const std::vector<T> &v) {
+    if (!alloc(v.size())) return false;
+    if (v.empty()) return true;
+    return hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+  }
+};
+
+inline int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+}  // namespace
+
+// ============================================================================
+// opaque handles
+// ============================================================================
+struct f12_basis {
+  int32_t ncenter = 0, nshell = 0, nprim = 0;
+  std::vector<double> xyz, exps, coefs;
+  std::vector<f12_shell> shells;
+};
+
+struct f12_pairs {
+  int32_t ordered = 0, nshell = 0;
+  int64_t nsp = 0, npp = 0;
+  // host copies used for enumeration
+  std::vector<int32_t> sa, sb, la, lb, ka, kb;
+  std::vector<int64_t> pp_off;
+  DevBuf<int32_t> d_sa, d_sb, d_la, d_lb, d_ka, d_kb;
+  DevBuf<int64_t> d_pp_off;
+  DevBuf<double> d_ABx, d_ABy, d_ABz;
+  DevBuf<double> d_ea, d_eb, d_p, d_Px, d_Py, d_Pz, d_cab;
+  PairsDev dev() const {
+    PairsDev d;
+    d.nsp = nsp;
+    d.npp = npp;
+    d.nshell = nshell;
+    d.ordered = ordered;
+    d.sa = d_sa.ptr;
+    d.sb = d_sb.ptr;
+    d.la = d_la.ptr;
+    d.lb = d_lb.ptr;
+    d.ka = d_ka.ptr;
+    d.kb = d_kb.ptr;
+    d.pp_off = d_pp_off.ptr;
+    d.ABx = d_ABx.ptr;
+    d.ABy = d_ABy.ptr;
+    d.ABz = d_ABz.ptr;
+    d.ea = d_ea.ptr;
+    d.eb = d_eb.ptr;
+    d.p = d_p.ptr;
+    d.Px = d_Px.ptr;
+    d.Py = d_Py.ptr;
+    d.Pz = d_Pz.ptr;
+    d.cab = d_cab.ptr;
+    return d;
+  }
+};
+
+struct HostTerm {
+  double c, alpha, b, g;
+};
+
+struct f12_kernel {
+  int32_t cls = 0;
+  std::vector<HostTerm> terms;
+  KernelDev host_desc;  // with device pointers filled in
+  DevBuf<KernelDev> d_desc;
+  std::vector<std::unique_ptr<DevBuf<double>>> tables;
+  DevBuf<double> d_phi;
+  int maxL = LTOT_MAX;
+};
+
+struct Bin {
+  int la, lb, lc, ld;
+  int64_t q0, nq;
+};
+
+struct f12_quartets {
+  const f12_pairs *bra = nullptr, *ket = nullptr;
+  int32_t cls = 0;
+  int64_t nq = 0, nout = 0, nprim = 0;
+  std::vector<int64_t> qb, qk, qoff, qprim;  // processing (= public) order
+  std::vector<Bin> bins;
+  DevBuf<int64_t> d_qb, d_qk, d_qoff, d_qprim;
+  DevBuf<double> d_A;
+  int64_t a_cap_prims = 0;
+};
+
+// ============================================================================
+// error strings
+// ============================================================================
+extern "C" const char *f12_strerror(int32_t s) {
+  switch (s) {
+    case F12_OK: return "ok";
+    case F12_EINVAL: return "invalid argument";
+    case F12_EPARAM: return "factor parameters rejected or unsupported";
+    case F12_ELMAX: return "angular momentum above the supported maximum";
+    case F12_ENOMEM: return "out of memory";
+    case F12_EDEVICE: return "HIP runtime error";
+    case F12_EBUFSIZE: return "output buffer too small";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int f12_stream_status(void *stream) {
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return F12_EDEVICE;
+  if (hipGetLastError() != hipSuccess) return F12_EDEVICE;
+  return F12_OK;
+}
+
+// ============================================================================
+// basis
+// ============================================================================
+extern "C" int f12_basis_create(int32_t ncenter, const double *xyz, int32_t nshell,
+                                const f12_shell *shells, int32_t nprim_total, const double *exps,
+                                const double *coefs, f12_basis **out) {
+  if (!out || ncenter <= 0 || nshell <= 0 || nprim_total <= 0 || !xyz || !shells || !exps ||
+      !coefs)
+    return F12_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < 3 * ncenter; ++i)
+    if (!std::isfinite(xyz[i])) return F12_EINVAL;
+  for (int i = 0; i < nprim_total; ++i)
+    if (!(exps[i] > 0.0) || !std::isfinite(exps[i]) || !std::isfinite(coefs[i])) return F12_EINVAL;
+  for (int s = 0; s < nshell; ++s) {
+    const f12_shell &sh = shells[s];
+    if (sh.l < 0) return F12_EINVAL;
+    if (sh.l > F12_LMAX) return F12_ELMAX;
+    if (sh.nprim <= 0 || sh.nprim > F12_MAX_KPRIM) return F12_EINVAL;
+    if (sh.center < 0 || sh.center >= ncenter) return F12_EINVAL;
+    if (sh.first_prim < 0 || sh.first_prim + sh.nprim > nprim_total) return F12_EINVAL;
+  }
+  f12_basis *b = new (std::nothrow) f12_basis;
+  if (!b) return F12_ENOMEM;
+  b->ncenter = ncenter;
+  b->nshell = nshell;
+  b->nprim = nprim_total;
+  b->xyz.assign(xyz, xyz + 3 * ncenter);
+  b->shells.assign(shells, shells + nshell);
+  b->exps.assign(exps, exps + nprim_total);
+  b->coefs.assign(coefs, coefs + nprim_total);
+  *out = b;
+  return F12_OK;
+}
+
+extern "C" void f12_basis_destroy(f12_basis *b) { delete b; }
+
+// ============================================================================
+// pairs
+// ============================================================================
+extern "C" int f12_pairs_build(const f12_basis *basis, int32_t ordered, void *stream,
+                               f12_pairs **out) {
+  if (!basis || !out || (ordered != 0 && ordered != 1)) return F12_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<f12_pairs> P(new (std::nothrow) f12_pairs);
+  if (!P) return F12_ENOMEM;
+  const int ns = basis->nshell;
+  P->ordered = ordered;
+  P->nshell = ns;
+  std::vector<double> ABx, ABy, ABz;
+  std::vector<int32_t> pp_sa, pp_sb, pp_ia, pp_ib;
+  int64_t npp = 0;
+  for (int i = 0; i < ns; ++i) {
+    int jmax = ordered ? ns - 1 : i;
+    for (int j = 0; j <= jmax; ++j) {
+      const f12_shell &a = basis->shells[i], &b = basis->shells[j];
+      P->sa.push_back(i);
+      P->sb.push_back(j);
+      P->la.push_back(a.l);
+      P->lb.push_back(b.l);
+      P->ka.push_back(a.nprim);
+      P->kb.push_back(b.nprim);
+      P->pp_off.push_back(npp);
+      const double *A = &basis->xyz[3 * a.center];
+      const double *B = &basis->xyz[3 * b.center];
+      ABx.push_back(A[0] - B[0]);
+      ABy.push_back(A[1] - B[1]);
+      ABz.push_back(A[2] - B[2]);
+      for (int ia = 0; ia < a.nprim; ++ia)
+        for (int ib = 0; ib < b.nprim; ++ib) {
+          pp_sa.push_back(i);
+          pp_sb.push_back(j);
+          pp_ia.push_back(ia);
+          pp_ib.push_back(ib);
+          ++npp;
+        }
+    }
+  }
+  P->nsp = (int64_t)P->sa.size();
+  P->npp = npp;
+  std::vector<int32_t> first(ns), center(ns);
+  for (int s = 0; s < ns; ++s) {
+    first[s] = basis->shells[s].first_prim;
+    center[s] = basis->shells[s].center;
+  }
+  DevBuf<int32_t> d_ppsa, d_ppsb, d_ppia, d_ppib, d_first, d_center;
+  DevBuf<double> d_xyz, d_exps, d_coefs;
+  bool ok = P->d_sa.upload(P->sa) && P->d_sb.upload(P->sb) && P->d_la.upload(P->la) &&
+            P->d_lb.upload(P->lb) && P->d_ka.upload(P->ka) && P->d_kb.upload(P->kb) &&
+            P->d_pp_off.upload(P->pp_off) && P->d_ABx.upload(ABx) && P->d_ABy.upload(ABy) &&
+            P->d_ABz.upload(ABz) && d_ppsa.upload(pp_sa) && d_ppsb.upload(pp_sb) &&
+            d_ppia.upload(pp_ia) && d_ppib.upload(pp_ib) && d_first.upload(first) &&
+            d_center.upload(center) && d_xyz.upload(basis->xyz) && d_exps.upload(basis->exps) &&
+            d_coefs.upload(basis->coefs) && P->d_ea.alloc(npp) && P->d_eb.alloc(npp) &&
+            P->d_p.alloc(npp) && P->d_Px.alloc(npp) && P->d_Py.alloc(npp) &&
+            P->d_Pz.alloc(npp) && P->d_cab.alloc(npp);
+  if (!ok) return F12_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  if (launch_pair_prims(npp, d_ppsa.ptr, d_ppsb.ptr, d_ppia.ptr, d_ppib.ptr, d_first.ptr,
+                        d_center.ptr, d_xyz.ptr, d_exps.ptr, d_coefs.ptr, P->d_ea.ptr,
+                        P->d_eb.ptr, P->d_p.ptr, P->d_Px.ptr, P->d_Py.ptr, P->d_Pz.ptr,
+                        P->d_cab.ptr, st) != 0)
+    return F12_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return F12_EDEVICE;
+  *out = P.release();
+  return F12_OK;
+}
+
+extern "C" int f12_pairs_count(const f12_pairs *p, int64_t *nsp, int64_t *npp) {
+  if (!p) return F12_EINVAL;
+  if (nsp) *nsp = p->nsp;
+  if (npp) *npp = p->npp;
+  return F12_OK;
+}
+
+extern "C" void f12_pairs_destroy(f12_pairs *p) { delete p; }
+
+// ============================================================================
+// kernel term tables (Eq. (rs12), Eq. (ttdamp), Eqs. (k1)-(k6))
+// ============================================================================
+namespace {
+
+using Expr = std::vector<HostTerm>;  // sum c r^alpha exp(b r - g r^2)
+
+bool same(double x, double y) { return std::fabs(x - y) <= 1e-12 * (1.0 + std::fabs(x) + std::fabs(y)); }
+
+void add_term(Expr &e, HostTerm t) {
+  if (t.c == 0.0) return;
+  for (auto &u : e)
+    if (same(u.alpha, t.alpha) && same(u.b, t.b) && same(u.g, t.g)) {
+      u.c += t.c;
+      return;
+    }
+  e.push_back(t);
+}
+
+Expr mul(const Expr &x, const Expr &y) {
+  Expr r;
+  for (auto &a : x)
+    for (auto &b : y) add_term(r, {a.c * b.c, a.alpha + b.alpha, a.b + b.b, a.g + b.g});
+  return r;
+}
+
+// d/dr [c r^a e^{b r - g r^2}] = c (a r^{a-1} + b r^a - 2 g r^{a+1}) e^{...}
+Expr deriv(const Expr &x) {
+  Expr r;
+  for (auto &t : x) {
+    add_term(r, {t.c * t.alpha, t.alpha - 1.0, t.b, t.g});
+    add_term(r, {t.c * t.b, t.alpha, t.b, t.g});
+    add_term(r, {-2.0 * t.c * t.g, t.alpha + 1.0, t.b, t.g});
+  }
+  return r;
+}
+
+Expr shift_alpha(const Expr &x, double d) {
+  Expr r = x;
+  for (auto &t : r) t.alpha += d;
+  return r;
+}
+
+// f(r) = (1 + r/2) e^{-mu r^2} + c0 r^rho e^{B r} - c0 sum_{k<=n} mu^k/k! r^{rho+2k} e^{B r - mu r^2}
+Expr factor_expr(const f12_factor &f) {
+  Expr e;
+  add_term(e, {1.0, 0.0, 0.0, f.mu});
+  add_term(e, {0.5, 1.0, 0.0, f.mu});
+  if (f.c0 != 0.0) {
+    add_term(e, {f.c0, f.rho, f.B, 0.0});
+    double mk = 1.0;
+    for (int k = 0; k <= f.n; ++k) {
+      if (k > 0) mk *= f.mu / k;
+      add_term(e, {-f.c0 * mk, f.rho + 2.0 * k, f.B, f.mu});
+    }
+  }
+  return e;
+}
+
+int validate_factor(const f12_factor *f) {
+  if (!f) return F12_EINVAL;
+  if (!std::isfinite(f->c0) || !std::isfinite(f->rho) || !std::isfinite(f->B) ||
+      !std::isfinite(f->mu))
+    return F12_EPARAM;
+  if (!(f->mu > 0.0)) return F12_EPARAM;
+  if (f->n < 0 || f->n > 8 || f->reserved != 0) return F12_EPARAM;
+  if (f->rho < -2.0 && !(f->n > -f->rho / 2.0 - 1.0)) return F12_EPARAM;
+  return F12_OK;
+}
+
+// --------------------------------------------------------------- DD Gamma ---
+// ln Gamma(z) by Stirling's series for z >= 40 (DD), shifted down by recurrence.
+dd dd_lgamma_large(dd z) {
+  // Bernoulli numbers B_2k as exact fractions
+  static const double num[] = {1, -1, 1, -1, 5, -691, 7, -3617, 43867, -174611, 854513, -236364091};
+  static const double den[] = {6, 30, 42, 30, 66, 2730, 6, 510, 798, 330, 138, 2730};
+  dd lz = dd_log(z);
+  dd r = dd_sub(dd_mul(dd_add(z, -0.5), lz), z);
+  // 0.5 ln(2 pi)
+  r = dd_add(r, dd{9.189385332046728e-01, -3.8782941580672414e-17});
+  dd zi = dd_div(dd_make(1.0), z);
+  dd z2 = dd_mul(zi, zi);
+  dd pw = zi;
+  for (int k = 1; k <= 12; ++k) {
+    dd bk = dd_div(dd_make(num[k - 1]), den[k - 1]);
+    dd term = dd_div(dd_mul(bk, pw), (double)(2 * k * (2 * k - 1)));
+    r = dd_add(r, term);
+    pw = dd_mul(pw, z2);
+  }
+  return r;
+}
+
+// Gamma(x) in DD for x > 0 (x given as a binary64 number).
+dd dd_gamma(double x) {
+  int N = 0;
+  dd z = dd_make(x);
+  dd prod = dd_make(1.0);
+  while (z.hi < 40.0) {
+    prod = dd_mul(prod, z);
+    z = dd_add(z, 1.0);
+    ++N;
+  }
+  dd lg = dd_lgamma_large(z);
+  return dd_div(dd_exp(lg), prod);
+}
+
+// Gamma(x) for x possibly <= 0 (non-integer): reflection by the recurrence upward.
+dd dd_gamma_any(double x) {
+  if (x > 0) return dd_gamma(x);
+  // Gamma(x) = Gamma(x + n) / (x (x+1) ... (x+n-1)), x + n > 0
+  dd prod = dd_make(1.0);
+  double y = x;
+  while (y <= 0.0) {
+    prod = dd_mul(prod, dd_make(y));
+    y += 1.0;
+  }
+  return dd_div(dd_gamma(y), prod);
+}
+
+// ---------------------------------------------------------- W-table builder ---
+// W_a(x) = R int_0^inf t^a exp(-(t-x)^2) dt for a = a0 + m, m in [m_lo, m_hi].
+//
+// Start values at the two regular orders a0 and a0+1 (a0 in [0,1)):
+//  * x >= 0: the confluent-hypergeometric form of S(alpha, beta, gamma) valid
+//    for either sign of beta (the Tricomi-U form of Eq. (suabz) holds only for
+//    beta <= 0): with z = x^2, a' = (a+1)/2,
+//      W_a(x) = exp(-z)/2 [Gamma(a') M(a',1/2,z) + 2x Gamma(a'+1/2) M(a'+1/2,3/2,z)],
+//    whose series has positive terms (Eq. (msmallz)).
+//  * x < 0: double-exponential quadrature of the (regular) integral.
+// Ladders by the integration-by-parts relation (Eq. (Srec1) with gamma = 1):
+//      W_{a+1} = x W_a + (a/2) W_{a-1}
+// run in the direction in which W is the dominant solution (upward for x > 0,
+// downward in a for x < 0 above a0 and for |x| small below a0); elsewhere
+// Miller's method: a trial solution started far away in the stable direction
+// and normalised at a0 (the paper's treatment of T_s for small gamma/beta^2).
+typedef long double ld;
+
+ld M_series_scaled(ld a, ld b, ld z) {
+  // exp(-z) M(a, b, z), positive terms
+  ld term = expl(-z);
+  ld sum = term;
+  for (int n = 1; n < 20000; ++n) {
+    term *= (a + n - 1) * z / ((b + n - 1) * n);
+    sum += term;
+    if (n > z && term < 1e-24L * sum) break;
+  }
+  return sum;
+}
+
+ld W_pos(ld a, ld x) {
+  ld ap = (a + 1) * 0.5L;
+  ld z = x * x;
+  ld g1 = tgammal(ap), g2 = tgammal(ap + 0.5L);
+  return 0.5L * (g1 * M_series_scaled(ap, 0.5L, z) + 2 * x * g2 * M_series_scaled(ap + 0.5L, 1.5L, z));
+}
+
+ld W_neg_quad(ld a, ld x) {
+  // exp-sinh: t = exp(pi/2 sinh s)
+  const ld h = 1.0L / 256;
+  const ld pi2 = 1.5707963267948966192313216916397514L;
+  ld sum = 0;
+  for (int k = -1536; k <= 1536; ++k) {
+    ld s = k * h;
+    ld t = expl(pi2 * sinhl(s));
+    if (t == 0 || !std::isfinite((double)t)) continue;
+    ld w = t * pi2 * coshl(s);
+    ld v = powl(t, a) * expl(-(t - x) * (t - x)) * w;
+    if (std::isfinite((double)v)) sum += v;
+  }
+  return sum * h;
+}
+
+// W_a(x) = exp(-x^2)/2 sum_k Gamma((a+k+1)/2) (2x)^k/k! (Phi_a(y) expanded
+// about y = 0 with Phi_a^(k)(0) = Phi_{a+k}(0) = Gamma((a+k+1)/2)/2), in DD.
+double w_phi_series_dd(double a, double x) {
+  const dd y2 = dd_mul(dd_make(2.0 * x), 2.0 * x);  // (2x)^2
+  dd t0 = dd_gamma_any(0.5 * (a + 1.0));              // k = 0 term
+  dd t1 = dd_mul(dd_gamma_any(0.5 * (a + 2.0)), 2.0 * x);  // k = 1 term
+  dd sum = dd_add(t0, t1);
+  const int kmin = (int)(4.0 * x * x) + 40;
+  for (int k = 0; k < 4000; k += 2) {
+    // t_{k+2} = t_k (a+k+1)/2 (2x)^2 / ((k+1)(k+2))
+    t0 = dd_div(dd_mul(dd_mul(t0, 0.5 * (a + k + 1.0)), y2), (double)(k + 1) * (k + 2));
+    t1 = dd_div(dd_mul(dd_mul(t1, 0.5 * (a + k + 2.0)), y2), (double)(k + 2) * (k + 3));
+    sum = dd_add(sum, dd_add(t0, t1));
+    if (k > kmin && std::fabs(t0.hi) + std::fabs(t1.hi) < 1e-34 * std::fabs(sum.hi)) break;
+  }
+  dd e = dd_exp(dd_neg(dd_mul(dd_make(x), x)));
+  return dd_to_double(dd_mul(dd_mul(sum, e), 0.5));
+}
+
+void w_column(double a0, bool is_int, int m_lo, int m_hi, double xd, double *out) {
+  const ld x = xd;
+  const int n = m_hi - m_lo + 1;
+  std::vector<ld> w(n, 0.0L);
+  auto at = [&](int m) -> ld & { return w[m - m_lo]; };
+  const ld A0 = a0;
+  ld w0, w1;
+  if (x >= 0) {
+    w0 = W_pos(A0, x);
+    w1 = W_pos(A0 + 1, x);
+  } else {
+    w0 = W_neg_quad(A0, x);
+    w1 = W_neg_quad(A0 + 1, x);
+  }
+  // ---- upward (m >= 0)
+  if (x > -0.5L) {
+    if (0 >= m_lo && 0 <= m_hi) at(0) = w0;
+    if (1 >= m_lo && 1 <= m_hi) at(1) = w1;
+    ld wm1 = w0, wc = w1;
+    for (int m = 1; m < m_hi; ++m) {
+      ld a = A0 + m;
+      ld wn = x * wc + 0.5L * a * wm1;
+      wm1 = wc;
+      wc = wn;
+      if (m + 1 >= m_lo) at(m + 1) = wn;
+    }
+  } else {
+    // Miller downward (W is the minimal solution as a grows); the ratio of the
+    // two solutions per step tends to 1 as x -> 0-, so start further up there.
+    int top = std::max(m_hi, 1) + 60 + (int)(600.0L / fabsl(x));
+    std::vector<ld> tr(top + 2, 0.0L);
+    tr[top + 1] = 0.0L;
+    tr[top] = 1e-300L;
+    for (int m = top; m >= 1; --m) {
+      ld a = A0 + m;  // W_{a-1} = (2 W_{a+1} - 2x W_a)/a
+      tr[m - 1] = (2 * tr[m + 1] - 2 * x * tr[m]) / a;
+      if (fabsl(tr[m - 1]) > 1e300L) {
+        for (int k = m - 1; k <= top + 1; ++k) tr[k] *= 1e-300L;
+      }
+    }
+    ld scale = w0 / tr[0];
+    for (int m = std::max(0, m_lo); m <= m_hi; ++m) at(m) = tr[m] * scale;
+  }
+  // ---- downward (m < 0), non-integer families only
+  if (m_lo < 0 && !is_int) {
+    if (x > 0.5L && x <= 12.0L) {
+      // Below a = -x^2/2 the recurrence is oscillatory (neither direction is
+      // stable): sum the Phi-series directly in double-double,
+      //   W_a(x) = exp(-x^2)/2 sum_k Gamma((a+k+1)/2) (2x)^k / k!.
+      for (int m = m_lo; m < 0; ++m) at(m) = (ld)w_phi_series_dd(a0 + m, (double)x);
+    } else if (x > 0.5L) {
+      // Miller upward from m_lo - 80 (W dominant as a grows)
+      int bot = m_lo - 80;
+      int cnt = 1 - bot + 1;
+      std::vector<ld> tr(cnt + 1, 0.0L);
+      // index k <-> m = bot + k
+      tr[0] = 0.0L;
+      tr[1] = 1e-300L;
+      for (int k = 1; k < cnt; ++k) {
+        ld a = A0 + (bot + k);
+        tr[k + 1] = x * tr[k] + 0.5L * a * tr[k - 1];
+        if (fabsl(tr[k + 1]) > 1e300L)
+          for (int j = 0; j <= k + 1; ++j) tr[j] *= 1e-300L;
+      }
+      ld scale = w0 / tr[0 - bot];
+      for (int m = m_lo; m < 0; ++m) at(m) = tr[m - bot] * scale;
+    } else {
+      ld wp = w1, wc = w0;  // W_{a0+1}, W_{a0}
+      for (int m = 0; m > m_lo; --m) {
+        ld a = A0 + m;  // W_{a-1} = (2 W_{a+1} - 2x W_a)/a
+        ld wn = (2 * wp - 2 * x * wc) / a;
+        wp = wc;
+        wc = wn;
+        at(m - 1) = wn;
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) out[i] = (double)w[i];
+}
+
+}  // namespace
+
+// Diagnostic: a column of the W table as built on the host.
+extern "C" int f12_aux_w_column(double alpha0, int32_t is_int, int32_t m_lo, int32_t m_hi,
+                                double x, double *out) {
+  if (!out || m_hi < m_lo || m_hi < 1 || alpha0 < 0 || alpha0 >= 1) return F12_EINVAL;
+  if (is_int && m_lo < 0) return F12_EINVAL;
+  w_column(alpha0, is_int != 0, m_lo, m_hi, x, out);
+  return F12_OK;
+}
+
+extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_factor *fp,
+                                 f12_kernel **out) {
+  if (!out) return F12_EINVAL;
+  *out = nullptr;
+  if (cls < 1 || cls > 6) return F12_EINVAL;
+  if (cls != 1) {
+    int s = validate_factor(f);
+    if (s) return s;
+  }
+  if (!fp) fp = f;
+  if (cls == 4 || cls == 6) {
+    int s = validate_factor(fp);
+    if (s) return s;
+  }
+  std::unique_ptr<f12_kernel> K(new (std::nothrow) f12_kernel);
+  if (!K) return F12_ENOMEM;
+  K->cls = cls;
+  Expr e;
+  switch (cls) {
+    case 1: add_term(e, {1.0, 0.0, 0.0, 0.0}); break;
+    case 2: e = factor_expr(*f); break;
+    case 3:
+    case 5: e = shift_alpha(factor_expr(*f), 1.0); break;
+    case 4: e = shift_alpha(mul(factor_expr(*f), factor_expr(*fp)), 1.0); break;
+    case 6: e = shift_alpha(mul(deriv(factor_expr(*f)), deriv(factor_expr(*fp))), 1.0); break;
+  }
+  // drop exact cancellations
+  Expr e2;
+  for (auto &t : e)
+    if (std::fabs(t.c) > 1e-300) e2.push_back(t);
+  e = e2;
+  K->terms = e;
+  // ---- families and chains
+  struct Fam {
+    double a0;
+    bool is_int;
+    int m_lo, m_hi;
+  };
+  std::vector<Fam> fams;
+  struct Ch {
+    double b, g;
+    int fam;
+    std::vector<std::pair<int, double>> tm;
+  };
+  std::vector<Ch> chains;
+  for (auto &t : e) {
+    double fl = std::floor(t.alpha + 1e-9);
+    double a0 = t.alpha - fl;
+    if (a0 < 1e-9 || a0 > 1 - 1e-9) a0 = 0.0;
+    int m = (int)std::lround(t.alpha - a0);
+    int fi = -1;
+    for (size_t i = 0; i < fams.size(); ++i)
+      if (std::fabs(fams[i].a0 - a0) < 1e-9) fi = (int)i;
+    if (fi < 0) {
+      fams.push_back({a0, a0 == 0.0, 1 << 30, -(1 << 30)});
+      fi = (int)fams.size() - 1;
+    }
+    if (fams[fi].is_int && m < 0) return F12_EPARAM;  // negative integer powers not supported
+    if (t.alpha <= -2.0 + 1e-9) return F12_EPARAM;    // small-T series needs alpha > -2
+    int ci = -1;
+    for (size_t i = 0; i < chains.size(); ++i)
+      if (chains[i].fam == fi && same(chains[i].b, t.b) && same(chains[i].g, t.g)) ci = (int)i;
+    if (ci < 0) {
+      chains.push_back({t.b, t.g, fi, {}});
+      ci = (int)chains.size() - 1;
+    }
+    if (t.b < 0.0) return F12_EPARAM;  // the ladders assume b >= 0
+    chains[ci].tm.push_back({m, t.c});
+  }
+  if ((int)chains.size() > MAX_CHAINS || (int)e.size() > MAX_TERMS ||
+      (int)fams.size() > MAX_FAMILIES)
+    return F12_EPARAM;
+  KernelDev &D = K->host_desc;
+  std::memset(&D, 0, sizeof(D));
+  D.cls = cls;
+  D.nchains = (int)chains.size();
+  D.nfam = (int)fams.size();
+  int nt = 0;
+  for (size_t c = 0; c < chains.size(); ++c) {
+    ChainDesc &cd = D.chains[c];
+    cd.b = chains[c].b;
+    cd.g = chains[c].g;
+    cd.family = chains[c].fam;
+    cd.t_begin = nt;
+    cd.m_min = 1 << 30;
+    cd.m_max = -(1 << 30);
+    for (auto &pr : chains[c].tm) {
+      D.terms[nt].c = pr.second;
+      D.terms[nt].m = pr.first;
+      D.terms[nt].chain = (int)c;
+      ++nt;
+      cd.m_min = std::min(cd.m_min, pr.first);
+      cd.m_max = std::max(cd.m_max, pr.first);
+    }
+    cd.t_end = nt;
+    cd.phi_off = (int)c * 2 * (KPHI + 1);
+    Fam &F = fams[cd.family];
+    int lo = F.is_int ? 0 : cd.m_min - LTOT_MAX;
+    F.m_lo = std::min(F.m_lo, lo);
+    F.m_hi = std::max(F.m_hi, cd.m_max + KT + 1);
+  }
+  D.nterms = nt;
+  // ---- W tables
+  const int nx = (int)std::lround((WX_HI - WX_LO) * WX_INVH) + 1;
+  for (size_t fi = 0; fi < fams.size(); ++fi) {
+    Fam &F = fams[fi];
+    int nm = F.m_hi - F.m_lo + 1;
+    std::vector<double> tab((size_t)nx * nm);
+    std::vector<double> col(nm);
+    for (int ix = 0; ix < nx; ++ix) {
+      double x = WX_LO + ix / WX_INVH;
+      w_column(F.a0, F.is_int, F.m_lo, F.m_hi, x, col.data());
+      std::copy(col.begin(), col.end(), tab.begin() + (size_t)ix * nm);
+    }
+    auto buf = std::unique_ptr<DevBuf<double>>(new DevBuf<double>);
+    if (!buf->upload(tab)) return F12_ENOMEM;
+    FamilyDesc &fd = D.fam[fi];
+    fd.alpha0 = F.a0;
+    fd.is_int = F.is_int;
+    fd.m_lo = F.m_lo;
+    fd.m_hi = F.m_hi;
+    fd.nm = nm;
+    fd.nx = nx;
+    fd.table = buf->ptr;
+    K->tables.push_back(std::move(buf));
+  }
+  // ---- Phi-series coefficients for the small-T route (DD)
+  std::vector<double> phi((size_t)D.nchains * 2 * (KPHI + 1) * 2);
+  for (int c = 0; c < D.nchains; ++c) {
+    const ChainDesc &cd = D.chains[c];
+    double as = fams[cd.family].a0 + cd.m_min + 1;
+    for (int s = 0; s < 2; ++s) {
+      double a = as + s;
+      dd kf = dd_make(1.0);
+      for (int k = 0; k <= KPHI; ++k) {
+        if (k > 0) kf = dd_mul(kf, (double)k);
+        double arg = 0.5 * (a + 1.0 + k);
+        dd gval = dd_gamma_any(arg);
+        dd v = dd_div(dd_mul(gval, 0.5), kf);
+        size_t o = ((size_t)(c * 2 + s) * (KPHI + 1) + k) * 2;
+        phi[o] = v.hi;
+        phi[o + 1] = v.lo;
+      }
+    }
+  }
+  if (!K->d_phi.upload(phi)) return F12_ENOMEM;
+  D.phi = K->d_phi.ptr;
+  if (!K->d_desc.alloc(1)) return F12_ENOMEM;
+  if (hipMemcpy(K->d_desc.ptr, &D, sizeof(KernelDev), hipMemcpyHostToDevice) != hipSuccess)
+    return F12_EDEVICE;
+  *out = K.release();
+  return F12_OK;
+}
+
+extern "C" int f12_kernel_terms(const f12_kernel *k, int32_t *nterms, double *out, int32_t cap) {
+  if (!k || !nterms) return F12_EINVAL;
+  *nterms = (int32_t)k->terms.size();
+  if (out)
+    for (int i = 0; i < (int)k->terms.size() && i < cap; ++i) {
+      out[4 * i] = k->terms[i].c;
+      out[4 * i + 1] = k->terms[i].alpha;
+      out[4 * i + 2] = k->terms[i].b;
+      out[4 * i + 3] = k->terms[i].g;
+    }
+  return F12_OK;
+}
+
+extern "C" void f12_kernel_destroy(f12_kernel *k) { delete k; }
+
+// Diagnostic: A_n (n = 0..L) on the device for explicit (p, q, R) triples.
+// d_p, d_q, d_R: device double[n]; d_A: device double[(L+1) * n], A[k*n + i].
+extern "C" int f12_aux_radial(const f12_kernel *k, int64_t n, const double *d_p, const double *d_q,
+                              const double *d_R, int32_t L, int32_t route, double *d_A,
+                              void *stream) {
+  if (!k || n < 0 || L < 0 || L > LTOT_MAX || route < 0 || route > 2 ||
+      (n > 0 && (!d_p || !d_q || !d_R || !d_A)))
+    return F12_EINVAL;
+  if (launch_aux_points(k->d_desc.ptr, n, d_p, d_q, d_R, L, route, d_A, (hipStream_t)stream) != 0)
+    return F12_EDEVICE;
+  return F12_OK;
+}
+
+// ============================================================================
+// quartets
+// ============================================================================
+namespace {
+
+int finish_quartets(f12_quartets *Q, std::vector<int64_t> &qb, std::vector<int64_t> &qk) {
+  const f12_pairs *B = Q->bra, *K = Q->ket;
+  const int64_t nq = (int64_t)qb.size();
+  // bin by (la, lb, lc, ld) with a counting sort (stable)
+  auto key = [&](int64_t i) {
+    return ((B->la[qb[i]] * 4 + B->lb[qb[i]]) * 4 + K->la[qk[i]]) * 4 + K->lb[qk[i]];
+  };
+  std::vector<int64_t> cnt(257, 0);
+  for (int64_t i = 0; i < nq; ++i) cnt[key(i) + 1]++;
+  for (int k = 0; k < 256; ++k) cnt[k + 1] += cnt[k];
+  std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+  Q->qb.assign(nq, 0);
+  Q->qk.assign(nq, 0);
+  for (int64_t i = 0; i < nq; ++i) {
+    int64_t d = pos[key(i)]++;
+    Q->qb[d] = qb[i];
+    Q->qk[d] = qk[i];
+  }
+  qb.clear();
+  qb.shrink_to_fit();
+  qk.clear();
+  qk.shrink_to_fit();
+  Q->bins.clear();
+  for (int k = 0; k < 256; ++k) {
+    int64_t n = cnt[k + 1] - cnt[k];
+    if (n == 0) continue;
+    Q->bins.push_back({k >> 6, (k >> 4) & 3, (k >> 2) & 3, k & 3, cnt[k], n});
+  }
+  Q->qoff.assign(nq + 1, 0);
+  Q->qprim.assign(nq + 1, 0);
+  for (int64_t i = 0; i < nq; ++i) {
+    const int64_t b = Q->qb[i], k = Q->qk[i];
+    Q->qoff[i + 1] = Q->qoff[i] + (int64_t)ncart(B->la[b]) * ncart(B->lb[b]) * ncart(K->la[k]) *
+                                      ncart(K->lb[k]);
+    Q->qprim[i + 1] =
+        Q->qprim[i] + (int64_t)B->ka[b] * B->kb[b] * (int64_t)K->ka[k] * K->kb[k];
+  }
+  Q->nq = nq;
+  Q->nout = Q->qoff[nq];
+  Q->nprim = Q->qprim[nq];
+  if (!Q->d_qb.upload(Q->qb) || !Q->d_qk.upload(Q->qk) || !Q->d_qoff.upload(Q->qoff) ||
+      !Q->d_qprim.upload(Q->qprim))
+    return F12_ENOMEM;
+  Q->a_cap_prims = std::min<int64_t>(std::max<int64_t>(Q->nprim, 1), (int64_t)1 << 23);
+  if (!Q->d_A.alloc((size_t)Q->a_cap_prims * (LTOT_MAX + 1))) return F12_ENOMEM;
+  return F12_OK;
+}
+
+int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_end, double *d_out,
+               hipStream_t st);
+
+}  // namespace
+
+extern "C" int f12_quartets_from_list(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
+                                      const int32_t *quads, int64_t nq, f12_quartets **out,
+                                      int64_t *n_out_doubles) {
+  if (!bra || !ket || !out || nq < 0 || (nq > 0 && !quads) || cls < 1 || cls > 6)
+    return F12_EINVAL;
+  *out = nullptr;
+  if (!bra->ordered || !ket->ordered) return F12_EINVAL;
+  std::unique_ptr<f12_quartets> Q(new (std::nothrow) f12_quartets);
+  if (!Q) return F12_ENOMEM;
+  Q->bra = bra;
+  Q->ket = ket;
+  Q->cls = cls;
+  std::vector<int64_t> qb(nq), qk(nq);
+  const int64_t ns = bra->nshell;
+  for (int64_t i = 0; i < nq; ++i) {
+    for (int j = 0; j < 4; ++j)
+      if (quads[4 * i + j] < 0 || quads[4 * i + j] >= ns) return F12_EINVAL;
+    qb[i] = quads[4 * i] * ns + quads[4 * i + 1];
+    qk[i] = quads[4 * i + 2] * ns + quads[4 * i + 3];
+  }
+  int s = finish_quartets(Q.get(), qb, qk);
+  if (s) return s;
+  if (n_out_doubles) *n_out_doubles = Q->nout;
+  *out = Q.release();
+  return F12_OK;
+}
+
+extern "C" int f12_quartets_build(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
+                                  double screen_tol, const f12_kernel *screen_kernel, void *stream,
+                                  f12_quartets **out, int64_t *n_quartets,
+                                  int64_t *n_out_doubles) {
+  if (!bra || !ket || !out || cls < 1 || cls > 6) return F12_EINVAL;
+  *out = nullptr;
+  if (bra->ordered || ket->ordered) return F12_EINVAL;  // unordered pair sets
+  if (bra->nshell != ket->nshell) return F12_EINVAL;
+  if (screen_tol > 0 && !screen_kernel) return F12_EINVAL;
+  std::vector<double> Qb, Qk;
+  hipStream_t st = (hipStream_t)stream;
+  if (screen_tol > 0) {
+    // Q_ab = sqrt(max |(ab|k|ab)|) over the diagonal quartets of the pair set
+    auto diag = [&](const f12_pairs *P, std::vector<double> &Qv) -> int {
+      std::unique_ptr<f12_quartets> D(new (std::nothrow) f12_quartets);
+      if (!D) return F12_ENOMEM;
+      D->bra = P;
+      D->ket = P;
+      D->cls = screen_kernel->cls == 5 ? 3 : screen_kernel->cls;
+      std::vector<int64_t> qb(P->nsp), qk(P->nsp);
+      for (int64_t i = 0; i < P->nsp; ++i) qb[i] = qk[i] = i;
+      int s = finish_quartets(D.get(), qb, qk);
+      if (s) return s;
+      DevBuf<double> dout;
+      if (!dout.alloc(D->nout)) return F12_ENOMEM;
+      s = eval_range(D.get(), screen_kernel, 0, D->nq, dout.ptr, st);
+      if (s) return s;
+      std::vector<double> h(D->nout);
+      if (hipMemcpyAsync(h.data(), dout.ptr, D->nout * sizeof(double), hipMemcpyDeviceToHost,
+                         st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return F12_EDEVICE;
+      Qv.assign(P->nsp, 0.0);
+      for (int64_t i = 0; i < D->nq; ++i) {
+        double m = 0;
+        for (int64_t o = D->qoff[i]; o < D->qoff[i + 1]; ++o) m = std::max(m, std::fabs(h[o]));
+        Qv[D->qb[i]] = std::sqrt(m);
+      }
+      return F12_OK;
+    };
+    int s = diag(bra, Qb);
+    if (s) return s;
+    if (ket == bra)
+      Qk = Qb;
+    else if ((s = diag(ket, Qk)))
+      return s;
+  }
+  std::unique_ptr<f12_quartets> Q(new (std::nothrow) f12_quartets);
+  if (!Q) return F12_ENOMEM;
+  Q->bra = bra;
+  Q->ket = ket;
+  Q->cls = cls;
+  std::vector<int64_t> qb, qk;
+  const bool fold = (cls != 5);  // I5 has no bra-ket symmetry
+  for (int64_t b = 0; b < bra->nsp; ++b) {
+    int64_t kmax = fold ? std::min(b, ket->nsp - 1) : ket->nsp - 1;
+    for (int64_t k = 0; k <= kmax; ++k) {
+      if (screen_tol > 0 && Qb[b] * Qk[k] < screen_tol) continue;
+      qb.push_back(b);
+      qk.push_back(k);
+    }
+  }
+  int s = finish_quartets(Q.get(), qb, qk);
+  if (s) return s;
+  if (n_quartets) *n_quartets = Q->nq;
+  if (n_out_doubles) *n_out_doubles = Q->nout;
+  *out = Q.release();
+  return F12_OK;
+}
+
+extern "C" int f12_quartet_offsets(const f12_quartets *q, int64_t *offsets) {
+  if (!q || !offsets) return F12_EINVAL;
+  std::copy(q->qoff.begin(), q->qoff.end(), offsets);
+  return F12_OK;
+}
+
+extern "C" int f12_quartet_list(const f12_quartets *q, int32_t *quads) {
+  if (!q || !quads) return F12_EINVAL;
+  for (int64_t i = 0; i < q->nq; ++i) {
+    quads[4 * i] = q->bra->sa[q->qb[i]];
+    quads[4 * i + 1] = q->bra->sb[q->qb[i]];
+    quads[4 * i + 2] = q->ket->sa[q->qk[i]];
+    quads[4 * i + 3] = q->ket->sb[q->qk[i]];
+  }
+  return F12_OK;
+}
+
+extern "C" int f12_quartets_prim_count(const f12_quartets *q, int64_t *n) {
+  if (!q || !n) return F12_EINVAL;
+  *n = q->nprim;
+  return F12_OK;
+}
+
+extern "C" void f12_quartets_destroy(f12_quartets *q) { delete q; }
+
+// ============================================================================
+// evaluation
+// ============================================================================
+namespace {
+
+int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_end, double *d_out,
+               hipStream_t st) {
+  const PairsDev bra = Q->bra->dev(), ket = Q->ket->dev();
+  const int i5 = (Q->cls == 5);
+  const int64_t out_base = Q->qoff[q_begin];
+  for (const Bin &b : Q->bins) {
+    int64_t lo = std::max(b.q0, q_begin), hi = std::min(b.q0 + b.nq, q_end);
+    if (lo >= hi) continue;
+    const int L = b.la + b.lb + b.lc + b.ld + (i5 ? 2 : 0);
+    int64_t qa = lo;
+    while (qa < hi) {
+      // largest chunk [qa, qe) with at most a_cap_prims primitive quartets
+      int64_t limit = Q->qprim[qa] + Q->a_cap_prims;
+      int64_t qe = std::upper_bound(Q->qprim.begin() + qa + 1, Q->qprim.begin() + hi + 1, limit) -
+                   Q->qprim.begin() - 1;
+      if (qe <= qa) qe = qa + 1;
+      const int64_t p0 = Q->qprim[qa];
+      const int64_t np = Q->qprim[qe] - p0;
+      if (launch_aux(k->d_desc.ptr, bra, ket, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qprim.ptr, qa,
+                     qe - qa, p0, np, L, Q->d_A.ptr, st) != 0)
+        return F12_EDEVICE;
+      if (launch_contract(bra, ket, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qoff.ptr, Q->d_qprim.ptr, qa,
+                          qe - qa, p0, np, Q->d_A.ptr, b.la, b.lb, b.lc, b.ld, i5, d_out, out_base,
+                          st) != 0)
+        return F12_EDEVICE;
+      qa = qe;
+    }
+  }
+  return F12_OK;
+}
+
+}  // namespace
+
+extern "C" int f12_eval(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
+                        double *d_out, int64_t out_capacity, void *stream) {
+  if (!q || !k || !d_out || q_begin < 0 || q_end > q->nq || q_begin > q_end) return F12_EINVAL;
+  if (k->cls != q->cls) return F12_EINVAL;
+  if (q->qoff[q_end] - q->qoff[q_begin] > out_capacity) return F12_EBUFSIZE;
+  if (q_begin == q_end) return F12_OK;
+  return eval_range(q, k, q_begin, q_end, d_out, (hipStream_t)stream);
+}

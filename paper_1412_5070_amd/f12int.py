@@ -1,0 +1,237 @@
+"""ctypes binding of libf12int.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts numpy /
+torch arguments to the pointers and sizes the C ABI takes.  Importing it
+fails loudly if the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+# torch first: its HIP runtime (libamdhip64, same soname as /opt/rocm's) must be
+# the one the library binds to, otherwise torch cannot initialise the device.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libf12int.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1412_5070_amd/build_lib.py "
+                      "(or __graft_entry__.build())")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_c_i32, _c_i64, _c_dbl, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+_P = ctypes.POINTER
+
+
+class Factor(ctypes.Structure):
+    _fields_ = [("c0", _c_dbl), ("rho", _c_dbl), ("B", _c_dbl), ("mu", _c_dbl),
+                ("n", _c_i32), ("reserved", _c_i32)]
+
+    @staticmethod
+    def of(f):
+        return Factor(float(f.c0), float(f.rho), float(f.B), float(f.mu), int(f.n), 0)
+
+
+class ShellC(ctypes.Structure):
+    _fields_ = [("l", _c_i32), ("nprim", _c_i32), ("center", _c_i32), ("first_prim", _c_i32)]
+
+
+EXPORTS = {
+    "f12_basis_create": (_c_i32, [_c_i32, _P(_c_dbl), _c_i32, _P(ShellC), _c_i32, _P(_c_dbl), _P(_c_dbl), _P(_vp)]),
+    "f12_basis_destroy": (None, [_vp]),
+    "f12_pairs_build": (_c_i32, [_vp, _c_i32, _vp, _P(_vp)]),
+    "f12_pairs_count": (_c_i32, [_vp, _P(_c_i64), _P(_c_i64)]),
+    "f12_pairs_destroy": (None, [_vp]),
+    "f12_kernel_create": (_c_i32, [_c_i32, _P(Factor), _P(Factor), _P(_vp)]),
+    "f12_kernel_terms": (_c_i32, [_vp, _P(_c_i32), _P(_c_dbl), _c_i32]),
+    "f12_kernel_destroy": (None, [_vp]),
+    "f12_quartets_build": (_c_i32, [_vp, _vp, _c_i32, _c_dbl, _vp, _vp, _P(_vp), _P(_c_i64), _P(_c_i64)]),
+    "f12_quartets_from_list": (_c_i32, [_vp, _vp, _c_i32, _P(_c_i32), _c_i64, _P(_vp), _P(_c_i64)]),
+    "f12_quartet_offsets": (_c_i32, [_vp, _P(_c_i64)]),
+    "f12_quartet_list": (_c_i32, [_vp, _P(_c_i32)]),
+    "f12_quartets_prim_count": (_c_i32, [_vp, _P(_c_i64)]),
+    "f12_quartets_destroy": (None, [_vp]),
+    "f12_eval": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp]),
+    "f12_aux_radial": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _c_i32, _c_i32, _vp, _vp]),
+    "f12_aux_w_column": (_c_i32, [_c_dbl, _c_i32, _c_i32, _c_i32, _c_dbl, _P(_c_dbl)]),
+    "f12_stream_status": (_c_i32, [_vp]),
+    "f12_strerror": (ctypes.c_char_p, [_c_i32]),
+}
+for _name, (_res, _args) in EXPORTS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class F12Error(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {_lib.f12_strerror(status).decode()} (status {status})")
+        self.status = status
+
+
+def _check(status, where):
+    if status != 0:
+        raise F12Error(status, where)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_P(_c_dbl))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return _vp(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _vp(stream)
+    return _vp(stream.cuda_stream)
+
+
+class Basis:
+    """Contracted Cartesian shells on centres (copied into the library)."""
+
+    def __init__(self, centers, shell_table, exps, coefs):
+        centers = np.ascontiguousarray(centers, dtype=np.float64).reshape(-1, 3)
+        st = np.ascontiguousarray(shell_table, dtype=np.int32).reshape(-1, 4)
+        self.exps = np.ascontiguousarray(exps, dtype=np.float64)
+        self.coefs = np.ascontiguousarray(coefs, dtype=np.float64)
+        shells = (ShellC * len(st))(*[ShellC(*map(int, row)) for row in st])
+        self.shell_l = st[:, 0].copy()
+        self.handle = _vp()
+        _check(_lib.f12_basis_create(len(centers), _dptr(centers), len(st), shells, len(self.exps),
+                                     _dptr(self.exps), _dptr(self.coefs), ctypes.byref(self.handle)),
+               "f12_basis_create")
+
+    @staticmethod
+    def from_shells(shells):
+        from synth import shells_to_arrays
+        return Basis(*shells_to_arrays(shells))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.f12_basis_destroy(h)
+        self.handle = None
+
+
+class Pairs:
+    def __init__(self, basis, ordered, stream=None):
+        self.basis = basis
+        self.handle = _vp()
+        _check(_lib.f12_pairs_build(basis.handle, int(ordered), _stream_ptr(stream), ctypes.byref(self.handle)),
+               "f12_pairs_build")
+        nsp, npp = _c_i64(), _c_i64()
+        _lib.f12_pairs_count(self.handle, ctypes.byref(nsp), ctypes.byref(npp))
+        self.n_shell_pairs, self.n_prim_pairs = nsp.value, npp.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.f12_pairs_destroy(h)
+        self.handle = None
+
+
+class Kernel:
+    """Kernel k_i of class `cls` for factors f (and fp for I4/I6)."""
+
+    def __init__(self, cls, f=None, fp=None):
+        self.cls = int(cls)
+        self.handle = _vp()
+        fc = Factor.of(f) if f is not None else Factor(0, 0, 0, 1, 0, 0)
+        fpc = Factor.of(fp) if fp is not None else None
+        _check(_lib.f12_kernel_create(self.cls, ctypes.byref(fc), ctypes.byref(fpc) if fpc else None,
+                                      ctypes.byref(self.handle)), "f12_kernel_create")
+
+    def terms(self):
+        n = _c_i32()
+        _check(_lib.f12_kernel_terms(self.handle, ctypes.byref(n), None, 0), "f12_kernel_terms")
+        out = np.zeros(4 * n.value)
+        _check(_lib.f12_kernel_terms(self.handle, ctypes.byref(n), _dptr(out), n.value), "f12_kernel_terms")
+        return out.reshape(-1, 4)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.f12_kernel_destroy(h)
+        self.handle = None
+
+
+class Quartets:
+    def __init__(self, handle, nq, nout, bra, ket, cls):
+        self.handle, self.n_quartets, self.n_out, self.bra, self.ket, self.cls = handle, nq, nout, bra, ket, cls
+
+    @staticmethod
+    def build(bra, ket, cls, screen_tol=0.0, screen_kernel=None, stream=None):
+        h, nq, nout = _vp(), _c_i64(), _c_i64()
+        _check(_lib.f12_quartets_build(bra.handle, ket.handle, int(cls), float(screen_tol),
+                                       screen_kernel.handle if screen_kernel else None, _stream_ptr(stream),
+                                       ctypes.byref(h), ctypes.byref(nq), ctypes.byref(nout)),
+               "f12_quartets_build")
+        return Quartets(h, nq.value, nout.value, bra, ket, cls)
+
+    @staticmethod
+    def from_list(bra, ket, cls, quads):
+        q = np.ascontiguousarray(quads, dtype=np.int32).reshape(-1, 4)
+        h, nout = _vp(), _c_i64()
+        _check(_lib.f12_quartets_from_list(bra.handle, ket.handle, int(cls), q.ctypes.data_as(_P(_c_i32)),
+                                           len(q), ctypes.byref(h), ctypes.byref(nout)), "f12_quartets_from_list")
+        return Quartets(h, len(q), nout.value, bra, ket, cls)
+
+    def offsets(self):
+        o = np.zeros(self.n_quartets + 1, dtype=np.int64)
+        _check(_lib.f12_quartet_offsets(self.handle, o.ctypes.data_as(_P(_c_i64))), "f12_quartet_offsets")
+        return o
+
+    def quads(self):
+        q = np.zeros((self.n_quartets, 4), dtype=np.int32)
+        _check(_lib.f12_quartet_list(self.handle, q.ctypes.data_as(_P(_c_i32))), "f12_quartet_list")
+        return q
+
+    def n_prim(self):
+        n = _c_i64()
+        _check(_lib.f12_quartets_prim_count(self.handle, ctypes.byref(n)), "f12_quartets_prim_count")
+        return n.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.f12_quartets_destroy(h)
+        self.handle = None
+
+
+def eval_into(quartets, kernel, out, q_begin=0, q_end=None, stream=None):
+    """Enqueue f12_eval writing blocks [q_begin, q_end) into the float64 CUDA tensor `out`."""
+    import torch
+    if q_end is None:
+        q_end = quartets.n_quartets
+    assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+    _check(_lib.f12_eval(quartets.handle, kernel.handle, int(q_begin), int(q_end), _vp(out.data_ptr()),
+                         out.numel(), _stream_ptr(stream)), "f12_eval")
+    return out
+
+
+def stream_status(stream=None):
+    _check(_lib.f12_stream_status(_stream_ptr(stream)), "f12_stream_status")
+
+
+def aux_radial(kernel, p, q, R, L, stream=None, route=0):
+    """A_n, n = 0..L, on the device for (p, q, R) triples; returns a float64 CUDA tensor (L+1, n)."""
+    import torch
+    dev = torch.device("cuda")
+    p = torch.as_tensor(p, dtype=torch.float64, device=dev).contiguous()
+    q = torch.as_tensor(q, dtype=torch.float64, device=dev).contiguous()
+    R = torch.as_tensor(R, dtype=torch.float64, device=dev).contiguous()
+    n = p.numel()
+    A = torch.empty((L + 1) * n, dtype=torch.float64, device=dev)
+    _check(_lib.f12_aux_radial(kernel.handle, n, _vp(p.data_ptr()), _vp(q.data_ptr()), _vp(R.data_ptr()),
+                               int(L), int(route), _vp(A.data_ptr()), _stream_ptr(stream)), "f12_aux_radial")
+    return A.view(L + 1, n)
+
+
+def aux_w_column(alpha0, is_int, m_lo, m_hi, x):
+    """Host-side table builder's W_a(x), a = alpha0 + m_lo..m_hi (numpy)."""
+    out = np.zeros(m_hi - m_lo + 1)
+    _check(_lib.f12_aux_w_column(float(alpha0), int(is_int), int(m_lo), int(m_hi), float(x), _dptr(out)),
+           "f12_aux_w_column")
+    return out
