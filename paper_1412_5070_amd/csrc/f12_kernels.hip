@@ -412,89 +412,128 @@ __global__ void __launch_bounds__(128) aux_kernel(const KernelDev *__restrict__ 
 //   E_0^{i,j+1} =  (a/p) AB E_0^{ij} + E_1^{ij}
 //   F_0^{i,j+1} =  (a/p) AB F_0^{ij} + F_1^{ij} + (a/p) E_0^{ij}
 //   E_t^{ij} = (i E_{t-1}^{i-1,j} + j E_{t-1}^{i,j-1}) / (2 p t), same for F.
-// Layout E[(i * 4 + j) * 7 + t].
+// Layout E[(i * (lb+1) + j) * (la+lb+1) + t].
 // ---------------------------------------------------------------------------
-#define EIDX(i, j, t) (((i) * (LMAX + 1) + (j)) * (2 * LMAX + 1) + (t))
-constexpr int E1D = (LMAX + 1) * (LMAX + 1) * (2 * LMAX + 1);
 
 __device__ void e_table(double a, double b, double AB, int la, int lb, double *E, double *Fd) {
-  for (int k = 0; k < E1D; ++k) {
+  const int nj = lb + 1, ntt = la + lb + 1;
+#define EI(i, j, t) (((i) * nj + (j)) * ntt + (t))
+  const int ne = (la + 1) * nj * ntt;
+  for (int k = 0; k < ne; ++k) {
     E[k] = 0.0;
     if (Fd) Fd[k] = 0.0;
   }
   const double p = a + b;
   const double mu = a * b / p;
   const double i2p = 0.5 / p;
-  E[EIDX(0, 0, 0)] = exp(-mu * AB * AB);
-  if (Fd) Fd[EIDX(0, 0, 0)] = -2.0 * mu * AB * E[EIDX(0, 0, 0)];
+  E[EI(0, 0, 0)] = exp(-mu * AB * AB);
+  if (Fd) Fd[EI(0, 0, 0)] = -2.0 * mu * AB * E[EI(0, 0, 0)];
   for (int N = 1; N <= la + lb; ++N) {
     for (int i = (N - lb > 0 ? N - lb : 0); i <= (la < N ? la : N); ++i) {
       const int j = N - i;
       for (int t = 1; t <= N; ++t) {
         double v = 0.0, w = 0.0;
         if (i > 0) {
-          v += i * E[EIDX(i - 1, j, t - 1)];
-          if (Fd) w += i * Fd[EIDX(i - 1, j, t - 1)];
+          v += i * E[EI(i - 1, j, t - 1)];
+          if (Fd) w += i * Fd[EI(i - 1, j, t - 1)];
         }
         if (j > 0) {
-          v += j * E[EIDX(i, j - 1, t - 1)];
-          if (Fd) w += j * Fd[EIDX(i, j - 1, t - 1)];
+          v += j * E[EI(i, j - 1, t - 1)];
+          if (Fd) w += j * Fd[EI(i, j - 1, t - 1)];
         }
-        E[EIDX(i, j, t)] = v * i2p / t;
-        if (Fd) Fd[EIDX(i, j, t)] = w * i2p / t;
+        E[EI(i, j, t)] = v * i2p / t;
+        if (Fd) Fd[EI(i, j, t)] = w * i2p / t;
       }
       if (i > 0) {
         const double c = -(b / p) * AB;
-        E[EIDX(i, j, 0)] = c * E[EIDX(i - 1, j, 0)] + E[EIDX(i - 1, j, 1)];
+        E[EI(i, j, 0)] = c * E[EI(i - 1, j, 0)] + E[EI(i - 1, j, 1)];
         if (Fd)
-          Fd[EIDX(i, j, 0)] = c * Fd[EIDX(i - 1, j, 0)] + Fd[EIDX(i - 1, j, 1)] -
-                              (b / p) * E[EIDX(i - 1, j, 0)];
+          Fd[EI(i, j, 0)] = c * Fd[EI(i - 1, j, 0)] + Fd[EI(i - 1, j, 1)] -
+                              (b / p) * E[EI(i - 1, j, 0)];
       } else {
         const double c = (a / p) * AB;
-        E[EIDX(i, j, 0)] = c * E[EIDX(i, j - 1, 0)] + E[EIDX(i, j - 1, 1)];
+        E[EI(i, j, 0)] = c * E[EI(i, j - 1, 0)] + E[EI(i, j - 1, 1)];
         if (Fd)
-          Fd[EIDX(i, j, 0)] = c * Fd[EIDX(i, j - 1, 0)] + Fd[EIDX(i, j - 1, 1)] +
-                              (a / p) * E[EIDX(i, j - 1, 0)];
+          Fd[EI(i, j, 0)] = c * Fd[EI(i, j - 1, 0)] + Fd[EI(i, j - 1, 1)] +
+                              (a / p) * E[EI(i, j - 1, 0)];
       }
     }
   }
 }
+#undef EI
 
 // ---------------------------------------------------------------------------
-// K5/K6: one workgroup per contracted quartet.  For each bra primitive pair:
-//   R^(0)_tuv from A_n by the MD recurrence (X = Q - P)
-//     R^(n)_{t+1,u,v} = t R^(n+1)_{t-1,u,v} + X_x R^(n+1)_{tuv}   (Eq. (ri))
-//   W[h][cd] += c_c c_d sum_{h' in box(cd)} E^cd_h' R_{h+h'}     (ket, Eq. (ii))
-// then I[ab][cd] += c_a c_b sum_h (-1)^|h| E^ab_h W[h][cd]        (bra, Eq. (ii)).
-// I5 (Eq. (I5byI3_) with the gradient coefficient -1, which is what
-// 1/2(lap_A - lap_B) = (a-b)/(2p) lap_Q - grad_Q . grad_AB gives):
-//   comp 0: (a-b)/(2p) E^ab_h  with  R_{h+h'+2x} + R_{h+h'+2y} + R_{h+h'+2z}
-//   comp d: -F^ab_{h,d}        with  R_{h+h'+e_d}
+// K5/K6: E.R.E contraction, one workgroup (256 threads) per contracted
+// quartet.  The threads form NG = 256/GS groups of GS lanes inside one
+// wavefront (so a group needs only wave-level synchronisation); group g
+// takes the ket primitive pairs j = g, g+NG, ...  For each bra primitive
+// pair i and each of its ket pairs j a group
+//   * builds R_ij: R^(n)_{t+1,u,v} = t R^(n+1)_{t-1,u,v} + X_x R^(n+1)_{tuv}
+//     (Eq. (ri), X = Q - P), the last level stored as lines along v;
+//   * does the ket transform (Eq. (ii))
+//       W[t,u,v][cd] += c_c c_d sum_{t'u'} Ex[t'] Ey[u'] sum_{v'} Ez[v'] R[t+t',u+u',v+v']
+//     as 1-D convolutions of R lines held in registers: a task is one
+//     (t,u) line and one cd, with accumulators W[t,u,0..Lab-t-u] in
+//     registers across all of the group's j.
+// The group partials are then summed in LDS and the bra transform
+//   I[ab][cd] += c_a c_b sum_h (-1)^|h| E^ab_h W[h][cd]
+// runs over (ab, cd) elements.  Large classes walk cd in chunks so that
+// tasks fit TPT per lane.
+// I5 (Eq. (I5byI3_) with gradient coefficient -1, the value of
+// 1/2 (lap_A - lap_B) = (a-b)/(2p) lap_Q - grad_Q . grad_AB):
+//   comp 0: (a-b)/(2p) E^ab  with lines R[T+2,U,.] + R[T,U+2,.] + R[T,U,.+2]
+//   comp d: -F^ab_d           with lines shifted by one along d.
 // ---------------------------------------------------------------------------
-template <int NT, int MAXE>
-__global__ void __launch_bounds__(NT)
-    contract_kernel(PairsDev bra, PairsDev ket, const int64_t *__restrict__ qb,
-                    const int64_t *__restrict__ qk, const int64_t *__restrict__ qoff,
-                    const int64_t *__restrict__ qprim, int64_t qa, int64_t p0, int64_t np,
-                    const double *__restrict__ A, int la, int lb, int lc, int ld, int i5,
-                    double *__restrict__ out, int64_t out_base) {
+constexpr int LINEMAX = 2 * (2 * LMAX) + 3;  // Lv + Z + 2 + 1
+
+__device__ __forceinline__ void group_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+struct ContractArgs {
+  PairsDev bra, ket;
+  const int64_t *qb, *qk, *qoff, *qprim;
+  int64_t qa, p0, np;
+  const double *A;
+  int la, lb, lc, ld, i5;
+  int cd_chunk, nchunks;
+  double *out;
+  int64_t out_base;
+};
+
+constexpr int MAXI = 8;
+
+template <int GS, int TPT>
+__global__ void __launch_bounds__(256) contract_kernel(ContractArgs a) {
+  constexpr int NT = 256;
+  constexpr int NG = NT / GS;
   extern __shared__ double lds[];
   const int tid = threadIdx.x;
-  const int64_t q = qa + blockIdx.x;
+  const int g = tid / GS, lt = tid % GS;
+  const int64_t q = a.qa + blockIdx.x;
+  const int la = a.la, lb = a.lb, lc = a.lc, ld = a.ld, i5 = a.i5;
   const int Lab = la + lb, Lcd = lc + ld;
   const int L = Lab + Lcd + (i5 ? 2 : 0);
   const int nb = ncart(lb), nd = ncart(ld);
   const int nab = ncart(la) * nb, ncd = ncart(lc) * nd;
   const int HL = hsize(L), Hab = hsize(Lab);
-  double *Rc = lds;
-  double *Rn = Rc + HL;
-  double *W = Rn + HL;
-  double *Eb = W + Hab * ncd;  // 3 directions
-  double *Fb = Eb + 3 * E1D;
-  double *Ek = Fb + 3 * E1D;
-  int *tuv = (int *)(Ek + 3 * E1D);
+  const int nlines = (Lab + 1) * (Lab + 2) / 2;
+  const int cdc = a.cd_chunk;
+  // E tables: [i][j][t] with runtime strides per pair
+  const int Eab1 = (la + 1) * (lb + 1) * (Lab + 1);  // one direction, bra
+  const int Ecd1 = (lc + 1) * (ld + 1) * (Lcd + 1);  // one direction, ket
+  // LDS layout
+  double *Eb = lds;               // 3 * Eab1
+  double *Fb = Eb + 3 * Eab1;     // 3 * Eab1
+  double *Gr = Fb + 3 * Eab1;     // per group: R0[HL], R1[HL], Ek[3*Ecd1]
+  const int gstride = 2 * HL + 3 * Ecd1;
+  double *Wp = Gr + NG * gstride; // NG * Hab * cdc
+  int *tuv = (int *)(Wp + (size_t)NG * Hab * cdc);  // HL
+  int *lineoff = tuv + HL;                           // (L+1)^2
+  int *linetu = lineoff + (L + 1) * (L + 1);         // nlines
   for (int idx = tid; idx < HL; idx += NT) {
-    // invert ridx
     int N = 0;
     while (hsize(N) <= idx) ++N;
     int r = idx - (N > 0 ? hsize(N - 1) : 0);
@@ -502,125 +541,193 @@ __global__ void __launch_bounds__(NT)
     while ((s + 1) * (s + 2) / 2 <= r) ++s;
     int u = s - (r - s * (s + 1) / 2);
     int t = N - s;
-    int v = N - t - u;
-    tuv[idx] = t | (u << 8) | (v << 16);
+    tuv[idx] = t | (u << 8) | ((N - t - u) << 16);
   }
-  const int64_t bp = qb[q], kp = qk[q];
+  if (tid == 0) {
+    int off = 0;
+    for (int T = 0; T <= L; ++T)
+      for (int U = 0; U <= L - T; ++U) {
+        lineoff[T * (L + 1) + U] = off;
+        off += L - T - U + 1;
+      }
+    int k = 0;
+    for (int t = 0; t <= Lab; ++t)
+      for (int u = 0; u <= Lab - t; ++u) linetu[k++] = t | (u << 8);
+  }
+  __syncthreads();
+  const int64_t bp = a.qb[q], kp = a.qk[q];
+  const PairsDev &bra = a.bra, &ket = a.ket;
   const int nbra = bra.ka[bp] * bra.kb[bp];
   const int nket = ket.ka[kp] * ket.kb[kp];
   const double ABb[3] = {bra.ABx[bp], bra.ABy[bp], bra.ABz[bp]};
   const double ABk[3] = {ket.ABx[kp], ket.ABy[kp], ket.ABz[kp]};
-  const int64_t qp0 = qprim[q] - p0;
-  double Iacc[MAXE];
-#pragma unroll
-  for (int k = 0; k < MAXE; ++k) Iacc[k] = 0.0;
+  const int64_t qp0 = a.qprim[q] - a.p0;
+  const int64_t o = a.qoff[q] - a.out_base;
+  double *R0 = Gr + g * gstride;
+  double *R1 = R0 + HL;
+  double *Ek = R1 + HL;
   const int ncomp = i5 ? 4 : 1;
-  for (int comp = 0; comp < ncomp; ++comp) {
-    for (int ib = 0; ib < nbra; ++ib) {
-      const int64_t ppb = bra.pp_off[bp] + ib;
-      const double ea = bra.ea[ppb], eb = bra.eb[ppb], pb = bra.p[ppb];
-      const double Pb[3] = {bra.Px[ppb], bra.Py[ppb], bra.Pz[ppb]};
-      if (tid < 3) e_table(ea, eb, ABb[tid], la, lb, Eb + tid * E1D, i5 ? Fb + tid * E1D : nullptr);
-      for (int e = tid; e < Hab * ncd; e += NT) W[e] = 0.0;
-      for (int jk = 0; jk < nket; ++jk) {
-        const int64_t ppk = ket.pp_off[kp] + jk;
-        __syncthreads();  // previous users of Ek / Rc are done
-        if (tid < 3) e_table(ket.ea[ppk], ket.eb[ppk], ABk[tid], lc, ld, Ek + tid * E1D, nullptr);
-        const double Xq[3] = {ket.Px[ppk] - Pb[0], ket.Py[ppk] - Pb[1], ket.Pz[ppk] - Pb[2]};
-        const int64_t pl = qp0 + (int64_t)ib * nket + jk;
-        double *rc = Rc, *rn = Rn;
-        for (int n = L; n >= 0; --n) {
-          const int cnt = hsize(L - n);
-          for (int idx = tid; idx < cnt; idx += NT) {
-            const int code = tuv[idx];
-            const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
-            double val;
-            if (idx == 0) {
-              val = A[(int64_t)n * np + pl];
-            } else if (t > 0) {
-              val = Xq[0] * rc[ridx(t - 1, u, v)];
-              if (t > 1) val += (t - 1) * rc[ridx(t - 2, u, v)];
-            } else if (u > 0) {
-              val = Xq[1] * rc[ridx(t, u - 1, v)];
-              if (u > 1) val += (u - 1) * rc[ridx(t, u - 2, v)];
-            } else {
-              val = Xq[2] * rc[ridx(t, u, v - 1)];
-              if (v > 1) val += (v - 1) * rc[ridx(t, u, v - 2)];
-            }
-            rn[idx] = val;
-          }
-          __syncthreads();
-          double *tmp = rc;
-          rc = rn;
-          rn = tmp;
-        }
-        // ket transform
-        const double ckd = ket.cab[ppk];
-        const int dt = (comp == 1), du = (comp == 2), dv = (comp == 3);
-        for (int e = tid; e < Hab * ncd; e += NT) {
-          const int h = e / ncd, cd = e - h * ncd;
-          const int code = tuv[h];
-          const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
-          int cx, cy, cz, dx, dy, dz;
-          cart_comp(lc, cd / nd, cx, cy, cz);
-          cart_comp(ld, cd % nd, dx, dy, dz);
-          const double *ex = Ek + EIDX(cx, dx, 0);
-          const double *ey = Ek + E1D + EIDX(cy, dy, 0);
-          const double *ez = Ek + 2 * E1D + EIDX(cz, dz, 0);
-          double s = 0.0;
-          for (int tp = 0; tp <= cx + dx; ++tp) {
-            for (int up = 0; up <= cy + dy; ++up) {
-              const double exy = ex[tp] * ey[up];
-              for (int vp = 0; vp <= cz + dz; ++vp) {
-                const int T = t + tp, U = u + up, V = v + vp;
-                double r;
-                if (i5 && comp == 0)
-                  r = rc[ridx(T + 2, U, V)] + rc[ridx(T, U + 2, V)] + rc[ridx(T, U, V + 2)];
-                else
-                  r = rc[ridx(T + dt, U + du, V + dv)];
-                s += exy * ez[vp] * r;
-              }
-            }
-          }
-          W[e] += ckd * s;
-        }
-      }
-      __syncthreads();  // W complete
-      // bra transform
-      const double cb = bra.cab[ppb];
-      const double wlap = i5 ? (ea - eb) / (2.0 * pb) : 1.0;
+  for (int chunk = 0; chunk < a.nchunks; ++chunk) {
+    const int cd0 = chunk * cdc;
+    const int ncdc = (ncd - cd0 < cdc) ? (ncd - cd0) : cdc;
+    const int ntask = nlines * ncdc;
+    double Iacc[MAXI];
 #pragma unroll
-      for (int k = 0; k < MAXE; ++k) {
-        const int e = tid + k * NT;
-        if (e < nab * ncd) {
-          const int ab = e / ncd, cd = e - ab * ncd;
-          int ax, ay, az, bx, by, bz;
-          cart_comp(la, ab / nb, ax, ay, az);
-          cart_comp(lb, ab % nb, bx, by, bz);
-          const double *ex = ((i5 && comp == 1) ? Fb : Eb) + EIDX(ax, bx, 0);
-          const double *ey = ((i5 && comp == 2) ? Fb : Eb) + E1D + EIDX(ay, by, 0);
-          const double *ez = ((i5 && comp == 3) ? Fb : Eb) + 2 * E1D + EIDX(az, bz, 0);
-          double s = 0.0;
-          for (int t = 0; t <= ax + bx; ++t) {
-            for (int u = 0; u <= ay + by; ++u) {
-              const double exy = ex[t] * ey[u];
-              for (int v = 0; v <= az + bz; ++v) {
-                const double term = exy * ez[v] * W[ridx(t, u, v) * ncd + cd];
-                s += ((t + u + v) & 1) ? -term : term;
+    for (int k = 0; k < MAXI; ++k) Iacc[k] = 0.0;
+    for (int comp = 0; comp < ncomp; ++comp) {
+      const int dt = (comp == 1), du = (comp == 2), dv = (comp == 3);
+      for (int ib = 0; ib < nbra; ++ib) {
+        const int64_t ppb = bra.pp_off[bp] + ib;
+        const double ea = bra.ea[ppb], eb = bra.eb[ppb], pb = bra.p[ppb];
+        const double Pb0 = bra.Px[ppb], Pb1 = bra.Py[ppb], Pb2 = bra.Pz[ppb];
+        if (tid < 3) e_table(ea, eb, ABb[tid], la, lb, Eb + tid * Eab1, i5 ? Fb + tid * Eab1 : nullptr);
+        double acc[TPT][2 * LMAX + 1];
+#pragma unroll
+        for (int s = 0; s < TPT; ++s)
+#pragma unroll
+          for (int v = 0; v <= 2 * LMAX; ++v) acc[s][v] = 0.0;
+        for (int jk = g; jk < nket; jk += NG) {
+          const int64_t ppk = ket.pp_off[kp] + jk;
+          for (int dir = lt; dir < 3; dir += GS)
+            e_table(ket.ea[ppk], ket.eb[ppk], ABk[dir], lc, ld, Ek + dir * Ecd1, nullptr);
+          const double X0 = ket.Px[ppk] - Pb0, X1 = ket.Py[ppk] - Pb1, X2 = ket.Pz[ppk] - Pb2;
+          const int64_t pl = qp0 + (int64_t)ib * nket + jk;
+          double *rc = R0, *rn = R1;
+          for (int n = L; n >= 0; --n) {
+            const int cnt = hsize(L - n);
+            for (int idx = lt; idx < cnt; idx += GS) {
+              const int code = tuv[idx];
+              const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
+              double val;
+              if (idx == 0) {
+                val = a.A[(int64_t)n * a.np + pl];
+              } else if (t > 0) {
+                val = X0 * rc[ridx(t - 1, u, v)];
+                if (t > 1) val += (t - 1) * rc[ridx(t - 2, u, v)];
+              } else if (u > 0) {
+                val = X1 * rc[ridx(t, u - 1, v)];
+                if (u > 1) val += (u - 1) * rc[ridx(t, u - 2, v)];
+              } else {
+                val = X2 * rc[ridx(t, u, v - 1)];
+                if (v > 1) val += (v - 1) * rc[ridx(t, u, v - 2)];
+              }
+              if (n == 0)
+                rn[lineoff[t * (L + 1) + u] + v] = val;
+              else
+                rn[idx] = val;
+            }
+            group_sync();
+            double *tmp = rc;
+            rc = rn;
+            rn = tmp;
+          }
+          const double *Rl = rc;  // lines along v
+          const double ckd = ket.cab[ppk];
+#pragma unroll
+          for (int s = 0; s < TPT; ++s) {
+            const int k = lt + s * GS;
+            if (k < ntask) {
+              const int line = k / ncdc;
+              const int cd = cd0 + (k - line * ncdc);
+              const int tu = linetu[line];
+              const int t = tu & 255, u = tu >> 8;
+              const int Lv = Lab - t - u;
+              int cx, cy, cz, dx, dy, dz;
+              cart_comp(lc, cd / nd, cx, cy, cz);
+              cart_comp(ld, cd % nd, dx, dy, dz);
+              const double *ex = Ek + (cx * (ld + 1) + dx) * (Lcd + 1);
+              const double *ey = Ek + Ecd1 + (cy * (ld + 1) + dy) * (Lcd + 1);
+              const double *ez = Ek + 2 * Ecd1 + (cz * (ld + 1) + dz) * (Lcd + 1);
+              const int Z = cz + dz;
+              const int nlv = Lv + Z + 1;
+              for (int tp = 0; tp <= cx + dx; ++tp) {
+                const double wx = ex[tp] * ckd;
+                for (int up = 0; up <= cy + dy; ++up) {
+                  const double c = wx * ey[up];
+                  const int T = t + tp, U = u + up;
+                  double lbuf[LINEMAX];
+                  if (i5 && comp == 0) {
+                    const double *l1 = Rl + lineoff[(T + 2) * (L + 1) + U];
+                    const double *l2 = Rl + lineoff[T * (L + 1) + U + 2];
+                    const double *l3 = Rl + lineoff[T * (L + 1) + U] + 2;
+                    for (int v = 0; v < nlv; ++v) lbuf[v] = l1[v] + l2[v] + l3[v];
+                  } else {
+                    const double *l1 = Rl + lineoff[(T + dt) * (L + 1) + U + du] + dv;
+                    for (int v = 0; v < nlv; ++v) lbuf[v] = l1[v];
+                  }
+                  for (int vp = 0; vp <= Z; ++vp) {
+                    const double cz2 = c * ez[vp];
+#pragma unroll
+                    for (int v = 0; v <= 2 * LMAX; ++v)
+                      if (v <= Lv) acc[s][v] = fma(cz2, lbuf[v + vp], acc[s][v]);
+                  }
+                }
               }
             }
           }
-          Iacc[k] += cb * ((comp == 0) ? wlap : -1.0) * s;
+          group_sync();  // R / Ek reused by the next j of this group
         }
+        // group partials -> Wp[g][h][cd]
+        double *Wg = Wp + (size_t)g * Hab * cdc;
+        for (int e = lt; e < Hab * cdc; e += GS) Wg[e] = 0.0;
+        group_sync();
+#pragma unroll
+        for (int s = 0; s < TPT; ++s) {
+          const int k = lt + s * GS;
+          if (k < ntask) {
+            const int line = k / ncdc;
+            const int cdl = k - line * ncdc;
+            const int tu = linetu[line];
+            const int t = tu & 255, u = tu >> 8;
+            for (int v = 0; v <= Lab - t - u; ++v) Wg[ridx(t, u, v) * cdc + cdl] = acc[s][v];
+          }
+        }
+        __syncthreads();
+        for (int e = tid; e < Hab * cdc; e += NT) {
+          double sum = Wp[e];
+          for (int gg = 1; gg < NG; ++gg) sum += Wp[(size_t)gg * Hab * cdc + e];
+          Wp[e] = sum;
+        }
+        __syncthreads();
+        // bra transform
+        const double cb = bra.cab[ppb];
+        const double wlap = i5 ? (ea - eb) / (2.0 * pb) : 1.0;
+        const double cw = cb * ((comp == 0) ? wlap : -1.0);
+#pragma unroll
+        for (int k = 0; k < MAXI; ++k) {
+          const int e = tid + k * NT;
+          if (e < nab * ncdc) {
+            const int ab = e / ncdc, cdl = e - ab * ncdc;
+            int ax, ay, az, bx, by, bz;
+            cart_comp(la, ab / nb, ax, ay, az);
+            cart_comp(lb, ab % nb, bx, by, bz);
+            const double *ex = ((i5 && comp == 1) ? Fb : Eb) + (ax * (lb + 1) + bx) * (Lab + 1);
+            const double *ey = ((i5 && comp == 2) ? Fb : Eb) + Eab1 + (ay * (lb + 1) + by) * (Lab + 1);
+            const double *ez = ((i5 && comp == 3) ? Fb : Eb) + 2 * Eab1 + (az * (lb + 1) + bz) * (Lab + 1);
+            double sacc = 0.0;
+            for (int t = 0; t <= ax + bx; ++t) {
+              for (int u = 0; u <= ay + by; ++u) {
+                const double exy = ex[t] * ey[u];
+                for (int v = 0; v <= az + bz; ++v) {
+                  const double term = exy * ez[v] * Wp[ridx(t, u, v) * cdc + cdl];
+                  sacc += ((t + u + v) & 1) ? -term : term;
+                }
+              }
+            }
+            Iacc[k] += cw * sacc;
+          }
+        }
+        __syncthreads();  // before Eb / Wp are overwritten
       }
-      __syncthreads();  // before Eb / W are overwritten
     }
-  }
-  const int64_t o = qoff[q] - out_base;
 #pragma unroll
-  for (int k = 0; k < MAXE; ++k) {
-    const int e = tid + k * NT;
-    if (e < nab * ncd) out[o + e] = Iacc[k];
+    for (int k = 0; k < MAXI; ++k) {
+      const int e = tid + k * NT;
+      if (e < nab * ncdc) {
+        const int ab = e / ncdc, cdl = e - ab * ncdc;
+        a.out[o + (int64_t)ab * ncd + cd0 + cdl] = Iacc[k];
+      }
+    }
   }
 }
 
@@ -652,12 +759,58 @@ int launch_aux(const KernelDev *K, const PairsDev &bra, const PairsDev &ket, con
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-static size_t contract_lds_bytes(int la, int lb, int lc, int ld, int i5) {
+// Launch shape per class: GS lanes per group (a power of two <= 64), TPT
+// tasks per lane, cd chunk size; returns the LDS bytes.
+struct ContractShape {
+  int gs, tpt, cd_chunk, nchunks;
+  size_t lds;
+};
+
+static ContractShape contract_shape(int la, int lb, int lc, int ld, int i5) {
   auto hs = [](int L) { return (L + 1) * (L + 2) * (L + 3) / 6; };
   auto nc = [](int l) { return (l + 1) * (l + 2) / 2; };
-  int L = la + lb + lc + ld + (i5 ? 2 : 0);
-  size_t d = 2 * (size_t)hs(L) + (size_t)hs(la + lb) * nc(lc) * nc(ld) + 9 * (size_t)E1D;
-  return d * sizeof(double) + hs(L) * sizeof(int);
+  const int Lab = la + lb;
+  const int L = la + lb + lc + ld + (i5 ? 2 : 0);
+  const int nlines = (Lab + 1) * (Lab + 2) / 2;
+  const int ncd = nc(lc) * nc(ld);
+  const int nab = nc(la) * nc(lb);
+  ContractShape sh;
+  const int ntask = nlines * ncd;
+  if (ntask <= 64 * 4) {
+    int need = (ntask + 3) / 4;
+    int gs = 1;
+    while (gs < need) gs *= 2;
+    sh.gs = gs;
+    sh.tpt = 4;
+    sh.cd_chunk = ncd;
+  } else {
+    sh.gs = 64;
+    sh.tpt = 8;
+    sh.cd_chunk = (64 * 8) / nlines;
+    if (sh.cd_chunk > ncd) sh.cd_chunk = ncd;
+  }
+  // the bra transform keeps MAXI elements per thread
+  while ((size_t)nab * sh.cd_chunk > (size_t)256 * MAXI) --sh.cd_chunk;
+  sh.nchunks = (ncd + sh.cd_chunk - 1) / sh.cd_chunk;
+  const int NG = 256 / sh.gs;
+  const int HL = hs(L);
+  const int Eab1 = (la + 1) * (lb + 1) * (Lab + 1);
+  const int Ecd1 = (lc + 1) * (ld + 1) * (lc + ld + 1);
+  size_t d = 6 * (size_t)Eab1 + (size_t)NG * (2 * HL + 3 * Ecd1) + (size_t)NG * hs(Lab) * sh.cd_chunk;
+  size_t ints = HL + (size_t)(L + 1) * (L + 1) + nlines;
+  sh.lds = d * sizeof(double) + ints * sizeof(int);
+  return sh;
+}
+
+template <int GS, int TPT>
+static void launch_contract_t(const ContractArgs &a, unsigned nblocks, size_t lds, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)contract_kernel<GS, TPT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL((contract_kernel<GS, TPT>), dim3(nblocks), dim3(256), lds, st, a);
 }
 
 int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb, const int64_t *qk,
@@ -665,22 +818,39 @@ int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
                     int64_t np, const double *A, int la, int lb, int lc, int ld, int i5,
                     double *out, int64_t out_base, hipStream_t stream) {
   if (nqc <= 0) return 0;
-  size_t lds = contract_lds_bytes(la, lb, lc, ld, i5);
-  auto nc = [](int l) { return (l + 1) * (l + 2) / 2; };
-  int nel = nc(la) * nc(lb) * nc(lc) * nc(ld);
-  if (nel <= 64 * 4) {
-    hipLaunchKernelGGL((contract_kernel<64, 4>), dim3((unsigned)nqc), dim3(64), lds, stream, bra,
-                       ket, qb, qk, qoff, qprim, qa, p0, np, A, la, lb, lc, ld, i5, out, out_base);
-  } else {
-    static bool attr_set = false;
-    if (!attr_set) {
-      hipFuncSetAttribute((const void *)contract_kernel<256, 40>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      attr_set = true;
-    }
-    hipLaunchKernelGGL((contract_kernel<256, 40>), dim3((unsigned)nqc), dim3(256), lds, stream,
-                       bra, ket, qb, qk, qoff, qprim, qa, p0, np, A, la, lb, lc, ld, i5, out,
-                       out_base);
+  ContractShape sh = contract_shape(la, lb, lc, ld, i5);
+  if (sh.lds > 160 * 1024) return -1;
+  ContractArgs a;
+  a.bra = bra;
+  a.ket = ket;
+  a.qb = qb;
+  a.qk = qk;
+  a.qoff = qoff;
+  a.qprim = qprim;
+  a.qa = qa;
+  a.p0 = p0;
+  a.np = np;
+  a.A = A;
+  a.la = la;
+  a.lb = lb;
+  a.lc = lc;
+  a.ld = ld;
+  a.i5 = i5;
+  a.cd_chunk = sh.cd_chunk;
+  a.nchunks = sh.nchunks;
+  a.out = out;
+  a.out_base = out_base;
+  const unsigned nb = (unsigned)nqc;
+  switch (sh.gs * 10 + sh.tpt) {
+    case 14: launch_contract_t<1, 4>(a, nb, sh.lds, stream); break;
+    case 24: launch_contract_t<2, 4>(a, nb, sh.lds, stream); break;
+    case 44: launch_contract_t<4, 4>(a, nb, sh.lds, stream); break;
+    case 84: launch_contract_t<8, 4>(a, nb, sh.lds, stream); break;
+    case 164: launch_contract_t<16, 4>(a, nb, sh.lds, stream); break;
+    case 324: launch_contract_t<32, 4>(a, nb, sh.lds, stream); break;
+    case 644: launch_contract_t<64, 4>(a, nb, sh.lds, stream); break;
+    case 648: launch_contract_t<64, 8>(a, nb, sh.lds, stream); break;
+    default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
