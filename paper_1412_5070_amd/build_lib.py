@@ -1,28 +1,51 @@
-"""Build libf12int.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libf12int.so (HIP, gfx950) in-tree with hipcc.
+
+Each source is compiled to an object in parallel (the shape-specialised
+contraction kernels are spread over several files), then linked."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libf12int.so")
-SOURCES = ["f12_host.cpp", "f12_kernels.hip"]
+SOURCES = ["f12_host.cpp", "f12_kernels.hip"] + ["f12_big_lab%d.hip" % k for k in range(7)]
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
 
 
-def build(verbose=False):
+def build(verbose=False, jobs=None):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc, "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-x", "hip",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-result"] + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", LIB + ".tmp"]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc] + FLAGS + ["-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        return src, obj, r
+
+    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 4)))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(compile_one, SOURCES))
+    failed = [(s, r) for s, _, r in results if r.returncode != 0]
+    for s, r in failed:
+        sys.stderr.write("== %s\n%s%s" % (s, r.stdout, r.stderr))
+    if failed:
+        raise RuntimeError("hipcc failed building libf12int.so")
+    if verbose:
+        for s, _, r in results:
+            if r.stderr.strip():
+                sys.stderr.write(r.stderr)
+    cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950"] + [o for _, o, _ in results] + ["-o", LIB + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libf12int.so")
-    if verbose:
-        sys.stderr.write(r.stderr)
+        raise RuntimeError("hipcc failed linking libf12int.so")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,438 @@
+// E.R.E contraction specialised on the class shape (L_ab = l_a + l_b,
+// L_cd = l_c + l_d, I5 or not) for the classes with L_ab + L_cd (+2) > 4.
+//
+// One work-group of 256 threads per contracted quartet; all threads work on
+// one primitive quartet at a time.  Per primitive quartet (bra i, ket j):
+//   R     R^(n)_{t+1,u,v} = t R^(n+1)_{t-1,u,v} + X_x R^(n+1)_{tuv} from
+//         R^(n)_000 = A_n (Eq. (ri) in MD form, X = Q - P), level by level;
+//         the last level is stored as lines along v.
+//   z     Z[T,U][v][fz] = sum_phi E^fz_phi R[T,U,v+phi]
+//   y     Y[T][u,v][fy,fz] = sum_nu E^fy_nu Z[T,u+nu][v][fz]
+//   x     V[t,u,v][f] = sum_tau E^fx_tau Y[t+tau][u,v][fy,fz]
+// with the one-centre ket expansion x_C^f exp(-q x_Q^2) = sum E^f_phi
+// Lambda_phi(x_Q).  V is summed over ket primitives in registers: thread
+// slot s owns a fixed V element whose f_x is known at compile time, so the
+// x sums run unrolled on E coefficients held in registers.  Per bra
+// primitive the bra transform I[ab][f] += c_a c_b sum_h (-1)^{|h|} E^ab_h V[h][f]
+// (Eq. (ii)) accumulates in registers, and the exponent-free transfer
+// x_D^d = sum_k C(d,k) (C_x - D_x)^(d-k) x_C^k gives (ab|cd) at the end.
+// I5 (Eq. (I5byI3_) with gradient coefficient -1):
+//   comp 0: (a-b)/(2p) E^ab with R_lap = R_{t+2,u,v} + R_{t,u+2,v} + R_{t,u,v+2},
+//   comp d: -F^ab_d with R shifted by one along d.
+#pragma once
+#include "f12_common.h"
+
+namespace f12 {
+
+constexpr int hs3c(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
+constexpr int nc2c(int l) { return (l + 1) * (l + 2) / 2; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+constexpr int max_nab(int lab) {
+  int m = 0;
+  for (int la = 0; la <= LMAX; ++la) {
+    const int lb = lab - la;
+    if (lb >= 0 && lb <= LMAX) m = cmax(m, nc2c(la) * nc2c(lb));
+  }
+  return m;
+}
+constexpr int max_eab(int lab) {
+  int m = 0;
+  for (int la = 0; la <= LMAX; ++la) {
+    const int lb = lab - la;
+    if (lb >= 0 && lb <= LMAX) m = cmax(m, (la + 1) * (lb + 1) * (lab + 1));
+  }
+  return m;
+}
+constexpr int max_nf(int lcd) {
+  const int lcmin = lcd > LMAX ? lcd - LMAX : 0;
+  return hs3c(lcd) - hs3c(lcmin - 1);
+}
+
+template <int LAB, int LCD, bool I5>
+struct BigShape {
+  static constexpr int NT = 256;
+  static constexpr int LP = LAB + LCD;
+  static constexpr int L = LP + (I5 ? 2 : 0);
+  static constexpr int HL = hs3c(L);
+  static constexpr int HAB = hs3c(LAB);
+  static constexpr int NE = nc2c(LCD);   // E^f_phi per direction; also (fy, fz) pairs
+  static constexpr int NUV = nc2c(LAB);  // (u, v) pairs with u + v <= LAB
+  static constexpr int NF0 = hs3c(LCD);  // one-centre components with |f| <= LCD
+  static constexpr int NLL = nc2c(L);    // R lines (T, U), T + U <= L
+  static constexpr int RLS = L + 1;
+  static constexpr int NLP = nc2c(LP);   // z-pass lines
+  static constexpr int ZST = (LAB + 1) * (LCD + 1);
+  static constexpr int YST = NUV * NE;
+  static constexpr int NZT = NLP * (LAB + 1);
+  static constexpr int NYT = (LP + 1) * (LAB + 1) * (LCD + 1);
+  static constexpr int NEB = (I5 ? 6 : 3) * max_eab(LAB);
+  // LDS (doubles)
+  static constexpr int oRp = NEB;              // R levels (ping-pong), later R_lap lines
+  static constexpr int oRl = oRp + 2 * HL;     // R lines
+  static constexpr int oZ = oRl + NLL * RLS;
+  static constexpr int oY = oZ + NLP * ZST;
+  static constexpr int oEk = oY + (LP + 1) * YST;
+  static constexpr int DBL = oEk + 3 * NE + 8;  // + pad: loads past a line end stay inside
+  static constexpr int INTS = HL + NLP;
+  static constexpr size_t BYTES = (size_t)DBL * 8 + (size_t)INTS * 4;
+  // V slots: for each f_x, HAB * (#(fy,fz) with fy + fz <= LCD - fx) elements
+  static constexpr int cnt_fx(int fx) { return HAB * nc2c(LCD - fx); }
+  static constexpr int slots_fx(int fx) { return (cnt_fx(fx) + NT - 1) / NT; }
+  static constexpr int off_fx(int fx) {
+    int s = 0;
+    for (int k = 0; k < fx; ++k) s += slots_fx(k);
+    return s;
+  }
+  static constexpr int MAXW = off_fx(LCD + 1);
+  static constexpr int MAXU = (max_nab(LAB) * max_nf(LCD) + NT - 1) / NT;
+  static_assert(nc2c(LP) * (LP + 1) <= 2 * HL || !I5, "R_lap lines must fit the level buffers");
+  static_assert(HAB * NF0 <= DBL - oRp, "V staging must fit");
+  static_assert(max_nab(LAB) * max_nf(LCD) <= DBL - oRp, "(ab|f) staging must fit");
+};
+
+template <int NCOL, int STRIDE>
+__device__ __forceinline__ void load_col(const double *p, int last, double (&c)[NCOL]) {
+#pragma unroll
+  for (int w = 0; w < NCOL; ++w) c[w] = (w <= last) ? p[w * STRIDE] : 0.0;
+}
+
+template <int LAB, int LCD, bool I5>
+__global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
+  using S = BigShape<LAB, LCD, I5>;
+  constexpr int NT = S::NT, LP = S::LP, L = S::L, NE = S::NE;
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x;
+  const int la = a.la, lb = a.lb, lc = a.lc, ld = a.ld;
+  const int Eab1 = (la + 1) * (lb + 1) * (LAB + 1);
+  double *Eb = lds, *Fb = lds + 3 * Eab1;
+  double *Rp = lds + S::oRp, *Rl = lds + S::oRl, *Zb = lds + S::oZ, *Yb = lds + S::oY;
+  double *Ek = lds + S::oEk;
+  int *tuv = (int *)(lds + S::DBL);
+  int *linetu = tuv + S::HL;
+  for (int idx = tid; idx < S::HL; idx += NT) {
+    int N = 0;
+    while (hs3c(N) <= idx) ++N;
+    const int r = idx - hs3c(N - 1);
+    int s = 0;
+    while ((s + 1) * (s + 2) / 2 <= r) ++s;
+    const int u = s - (r - s * (s + 1) / 2);
+    const int t = N - s;
+    tuv[idx] = t | (u << 8) | ((N - t - u) << 16);
+  }
+  for (int line = tid; line < S::NLP; line += NT) {
+    int T = 0, base = 0;
+    while (base + (LP + 1 - T) <= line) {
+      base += LP + 1 - T;
+      ++T;
+    }
+    linetu[line] = T | ((line - base) << 8);
+  }
+  __syncthreads();
+
+  // V slot descriptors: Y offset of the slot's element (t, u, v, fy, fz), or -1
+  int ybase[S::MAXW];
+  double wacc[S::MAXW];
+#pragma unroll
+  for (int fx = 0; fx <= LCD; ++fx) {
+    const int M = LCD - fx;
+    const int nyz = (M + 1) * (M + 2) / 2;
+#pragma unroll
+    for (int k = 0; k < S::slots_fx(fx); ++k) {
+      const int slot = S::off_fx(fx) + k;
+      const int e = tid + NT * k;
+      ybase[slot] = -1;
+      if (e < S::cnt_fx(fx)) {
+        const int h = e / nyz, r = e - h * nyz;
+        int fy = 0, rr = r;
+        while (rr > M - fy) {
+          rr -= M - fy + 1;
+          ++fy;
+        }
+        const int fz = rr;
+        const int code = tuv[h];
+        const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
+        if (fx + fy + fz >= lc) {
+          const int uvi = u * (LAB + 1) - u * (u - 1) / 2 + v;
+          const int fyz = fy * (LCD + 1) - fy * (fy - 1) / 2 + fz;
+          ybase[slot] = t * S::YST + uvi * NE + fyz;
+        }
+      }
+    }
+  }
+
+  const int64_t q = a.qa + blockIdx.x;
+  const int64_t bp = a.qb[q], kp = a.qk[q];
+  const PairsDev &bra = a.bra, &ket = a.ket;
+  const int nbra = bra.ka[bp] * bra.kb[bp];
+  const int nket = ket.ka[kp] * ket.kb[kp];
+  const double ABb[3] = {bra.ABx[bp], bra.ABy[bp], bra.ABz[bp]};
+  const double CD[3] = {ket.ABx[kp], ket.ABy[kp], ket.ABz[kp]};
+  const double CD2 = CD[0] * CD[0] + CD[1] * CD[1] + CD[2] * CD[2];
+  const int64_t qp0 = a.qprim[q] - a.p0;
+  const int64_t o = a.qoff[q] - a.out_base;
+  const int nb = ncart(lb);
+  const int nf = hs3(LCD) - hs3(lc - 1);
+  const int foff = hs3(lc - 1);
+  const int nu = ncart(la) * nb * nf;
+
+  double uacc[S::MAXU];
+#pragma unroll
+  for (int k = 0; k < S::MAXU; ++k) uacc[k] = 0.0;
+
+  for (int ib = 0; ib < nbra; ++ib) {
+    const int64_t ppb = bra.pp_off[bp] + ib;
+    const double ea = bra.ea[ppb], eb = bra.eb[ppb], pb = bra.p[ppb];
+    const double Pb0 = bra.Px[ppb], Pb1 = bra.Py[ppb], Pb2 = bra.Pz[ppb];
+    const double cab = bra.cab[ppb];
+    if (tid < 3) e_table(ea, eb, ABb[tid], la, lb, Eb + tid * Eab1, I5 ? Fb + tid * Eab1 : nullptr);
+#pragma unroll 1
+    for (int comp = 0; comp < (I5 ? 4 : 1); ++comp) {
+#pragma unroll
+      for (int s = 0; s < S::MAXW; ++s) wacc[s] = 0.0;
+      const bool lap = I5 && comp == 0;
+      const int dt = comp == 1, du = comp == 2, dv = comp == 3;
+      for (int jk = 0; jk < nket; ++jk) {
+        const int64_t ppk = ket.pp_off[kp] + jk;
+        const double qk = ket.p[ppk], ed = ket.eb[ppk];
+        if (tid < 3) e_onecentre(qk, -(ed / qk) * CD[tid], LCD, Ek + tid * NE);
+        const double X0 = ket.Px[ppk] - Pb0, X1 = ket.Py[ppk] - Pb1, X2 = ket.Pz[ppk] - Pb2;
+        const double ckd = ket.cab[ppk] * exp(-(ket.ea[ppk] * ed / qk) * CD2);
+        const int64_t pl = qp0 + (int64_t)ib * nket + jk;
+        // R levels n = L..0; the last level goes to lines Rl[line(t,u)][v]
+        {
+          double *rc = Rp, *rn = Rp + S::HL;
+#pragma unroll 1
+          for (int n = L; n >= 0; --n) {
+            const int cnt = hs3(L - n);
+            for (int idx = tid; idx < cnt; idx += NT) {
+              const int code = tuv[idx];
+              const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
+              double val;
+              if (idx == 0) {
+                val = a.A[(int64_t)n * a.np + pl];
+              } else if (t > 0) {
+                val = X0 * rc[ridx(t - 1, u, v)];
+                if (t > 1) val += (t - 1) * rc[ridx(t - 2, u, v)];
+              } else if (u > 0) {
+                val = X1 * rc[ridx(t, u - 1, v)];
+                if (u > 1) val += (u - 1) * rc[ridx(t, u - 2, v)];
+              } else {
+                val = X2 * rc[ridx(t, u, v - 1)];
+                if (v > 1) val += (v - 1) * rc[ridx(t, u, v - 2)];
+              }
+              if (n == 0)
+                Rl[(t * (L + 1) - t * (t - 1) / 2 + u) * S::RLS + v] = val;
+              else
+                rn[idx] = val;
+            }
+            __syncthreads();
+            double *tmp = rc;
+            rc = rn;
+            rn = tmp;
+          }
+        }
+        if (lap) {
+          // R_lap lines over T + U <= LP, stride LP + 1, in the level buffers
+          for (int k = tid; k < S::NLP * (LP + 1); k += NT) {
+            const int line = k / (LP + 1), w = k - line * (LP + 1);
+            const int tu = linetu[line];
+            const int T = tu & 255, U = tu >> 8;
+            if (T + U + w > LP) continue;
+            const double r1 = Rl[((T + 2) * (L + 1) - (T + 2) * (T + 1) / 2 + U) * S::RLS + w];
+            const double r2 = Rl[(T * (L + 1) - T * (T - 1) / 2 + U + 2) * S::RLS + w];
+            const double r3 = Rl[(T * (L + 1) - T * (T - 1) / 2 + U) * S::RLS + w + 2];
+            Rp[line * (LP + 1) + w] = r1 + r2 + r3;
+          }
+          __syncthreads();
+        }
+        // z pass
+        {
+          double ez[NE];
+#pragma unroll
+          for (int k = 0; k < NE; ++k) ez[k] = Ek[2 * NE + k];
+          for (int k = tid; k < S::NZT; k += NT) {
+            const int line = k / (LAB + 1), v = k - line * (LAB + 1);
+            const int tu = linetu[line];
+            const int T = tu & 255, U = tu >> 8;
+            if (T + U + v > LP) continue;
+            const double *src;
+            int last;
+            if (lap) {
+              src = Rp + line * (LP + 1) + v;
+              last = LP - T - U - v;
+            } else {
+              const int Ts = T + dt, Us = U + du;
+              src = Rl + (Ts * (L + 1) - Ts * (Ts - 1) / 2 + Us) * S::RLS + v + dv;
+              last = L - Ts - Us - v - dv;
+            }
+            double r[LCD + 1];
+            load_col<LCD + 1, 1>(src, last, r);
+            double *zo = Zb + line * S::ZST + v * (LCD + 1);
+#pragma unroll
+            for (int fz = 0; fz <= LCD; ++fz) {
+              double acc = 0.0;
+#pragma unroll
+              for (int ph = 0; ph <= fz; ++ph) acc = fma(ez[fz * (fz + 1) / 2 + ph], r[ph], acc);
+              zo[fz] = acc;
+            }
+          }
+        }
+        __syncthreads();
+        // y pass
+        {
+          double ey[NE];
+#pragma unroll
+          for (int k = 0; k < NE; ++k) ey[k] = Ek[NE + k];
+          for (int k = tid; k < S::NYT; k += NT) {
+            const int fz = k % (LCD + 1);
+            const int r1 = k / (LCD + 1);
+            const int v = r1 % (LAB + 1), T = r1 / (LAB + 1);
+            if (T + v + fz > LP) continue;
+            const int line0 = T * (LP + 1) - T * (T - 1) / 2;
+            double col[LP + 1];
+            load_col<LP + 1, S::ZST>(Zb + line0 * S::ZST + v * (LCD + 1) + fz, LP - T, col);
+            double *yo = Yb + T * S::YST + v * NE + fz;
+#pragma unroll
+            for (int u = 0; u <= LAB; ++u) {
+              if (u + v > LAB) continue;
+              const int uo = (u * (LAB + 1) - u * (u - 1) / 2) * NE;
+#pragma unroll
+              for (int fy = 0; fy <= LCD; ++fy) {
+                if (fy + fz > LCD) continue;
+                double acc = 0.0;
+#pragma unroll
+                for (int nu = 0; nu <= fy; ++nu) acc = fma(ey[fy * (fy + 1) / 2 + nu], col[u + nu], acc);
+                yo[uo + fy * (LCD + 1) - fy * (fy - 1) / 2] = acc;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        // x pass into the register slots
+        {
+          double ex[NE];
+#pragma unroll
+          for (int k = 0; k < NE; ++k) ex[k] = Ek[k];
+#pragma unroll
+          for (int fx = 0; fx <= LCD; ++fx) {
+#pragma unroll
+            for (int k = 0; k < S::slots_fx(fx); ++k) {
+              const int slot = S::off_fx(fx) + k;
+              const int yb = ybase[slot];
+              if (yb >= 0) {
+                double acc = 0.0;
+#pragma unroll
+                for (int ta = 0; ta <= fx; ++ta) acc = fma(ex[fx * (fx + 1) / 2 + ta], Yb[yb + ta * S::YST], acc);
+                wacc[slot] = fma(ckd, acc, wacc[slot]);
+              }
+            }
+          }
+        }
+        __syncthreads();  // Ek, Y and R are rewritten for the next ket primitive
+      }
+      // stage V[h][f] (dense f over |f| <= LCD) for the bra transform
+      double *Vs = lds + S::oRp;
+#pragma unroll
+      for (int fx = 0; fx <= LCD; ++fx) {
+        const int M = LCD - fx;
+        const int nyz = (M + 1) * (M + 2) / 2;
+#pragma unroll
+        for (int k = 0; k < S::slots_fx(fx); ++k) {
+          const int slot = S::off_fx(fx) + k;
+          if (ybase[slot] >= 0) {
+            const int e = tid + NT * k;
+            const int h = e / nyz, r = e - h * nyz;
+            int fy = 0, rr = r;
+            while (rr > M - fy) {
+              rr -= M - fy + 1;
+              ++fy;
+            }
+            const int fz = rr;
+            const int n = fx + fy + fz, s2 = fy + fz;
+            Vs[h * S::NF0 + hs3(n - 1) + s2 * (s2 + 1) / 2 + fz] = wacc[slot];
+          }
+        }
+      }
+      __syncthreads();
+      const double cw = cab * (I5 ? (comp == 0 ? (ea - eb) / (2.0 * pb) : -1.0) : 1.0);
+#pragma unroll
+      for (int k = 0; k < S::MAXU; ++k) {
+        const int e = tid + NT * k;
+        if (e < nu) {
+          const int ab = e / nf, f = e - ab * nf + foff;
+          int ax, ay, az, bx, by, bz;
+          cart_comp(la, ab / nb, ax, ay, az);
+          cart_comp(lb, ab % nb, bx, by, bz);
+          const double *exr = (comp == 1 ? Fb : Eb) + (ax * (lb + 1) + bx) * (LAB + 1);
+          const double *eyr = (comp == 2 ? Fb : Eb) + Eab1 + (ay * (lb + 1) + by) * (LAB + 1);
+          const double *ezr = (comp == 3 ? Fb : Eb) + 2 * Eab1 + (az * (lb + 1) + bz) * (LAB + 1);
+          double sacc = 0.0;
+          for (int t = 0; t <= ax + bx; ++t)
+            for (int u = 0; u <= ay + by; ++u) {
+              const double exy = ((t + u) & 1) ? -exr[t] * eyr[u] : exr[t] * eyr[u];
+              double sv = 0.0;
+              for (int v = 0; v <= az + bz; ++v) {
+                const double term = ezr[v] * Vs[ridx(t, u, v) * S::NF0 + f];
+                sv += (v & 1) ? -term : term;
+              }
+              sacc = fma(exy, sv, sacc);
+            }
+          uacc[k] = fma(cw, sacc, uacc[k]);
+        }
+      }
+      __syncthreads();  // before V staging / E tables are overwritten
+    }
+  }
+  double *Uf = lds + S::oRp;
+#pragma unroll
+  for (int k = 0; k < S::MAXU; ++k) {
+    const int e = tid + NT * k;
+    if (e < nu) Uf[e] = uacc[k];
+  }
+  __syncthreads();
+  hrr_store(Uf, la, lb, lc, ld, nf, CD, a.out + o, tid, NT);
+}
+
+template <int LAB, int LCD, bool I5>
+inline int launch_big_t(const ContractArgs &a, unsigned nblocks, hipStream_t st) {
+  using S = BigShape<LAB, LCD, I5>;
+  static bool attr = false;
+  if (!attr) {
+    if (hipFuncSetAttribute((const void *)big_kernel<LAB, LCD, I5>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::BYTES) != hipSuccess)
+      return -1;
+    attr = true;
+  }
+  hipLaunchKernelGGL((big_kernel<LAB, LCD, I5>), dim3(nblocks), dim3(256), S::BYTES, st, a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Shapes handled here: L_ab + L_cd + (I5 ? 2 : 0) > 4.
+constexpr bool big_shape(int lab, int lcd, bool i5) { return lab + lcd + (i5 ? 2 : 0) > 4; }
+
+template <int LAB>
+inline int launch_big_lab(int lcd, int i5, const ContractArgs &a, unsigned nblocks, hipStream_t st) {
+#define F12_BIG_CASE(LCD)                                                              \
+  case LCD:                                                                            \
+    if (i5) {                                                                          \
+      if constexpr (big_shape(LAB, LCD, true)) return launch_big_t<LAB, LCD, true>(a, nblocks, st); \
+    } else {                                                                           \
+      if constexpr (big_shape(LAB, LCD, false)) return launch_big_t<LAB, LCD, false>(a, nblocks, st); \
+    }                                                                                  \
+    return -1;
+  switch (lcd) {
+    F12_BIG_CASE(0)
+    F12_BIG_CASE(1)
+    F12_BIG_CASE(2)
+    F12_BIG_CASE(3)
+    F12_BIG_CASE(4)
+    F12_BIG_CASE(5)
+    F12_BIG_CASE(6)
+    default:
+      return -1;
+  }
+#undef F12_BIG_CASE
+}
+
+}  // namespace f12

@@ -1,0 +1,187 @@
+// Device helpers shared by the contraction kernels (f12_kernels.hip and the
+// per-shape kernels f12_big_lab*.hip): Hermite index maps, Cartesian
+// component order, E coefficients and the launch argument block.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#include "f12_internal.h"
+
+namespace f12 {
+
+__device__ __forceinline__ int hsize(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
+// Hermite index of (t,u,v): by total N = t+u+v, then t descending, then u descending.
+__device__ __forceinline__ int ridx(int t, int u, int v) {
+  int N = t + u + v;
+  int s = N - t;
+  return N * (N + 1) * (N + 2) / 6 + s * (s + 1) / 2 + (s - u);
+}
+__device__ __forceinline__ int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+// Canonical Cartesian component c of angular momentum l: (i,k,m), i from l
+// down to 0, then k from l-i down to 0.
+__device__ __forceinline__ void cart_comp(int l, int c, int &i, int &k, int &m) {
+  int ii = l, base = 0;
+  while (c >= base + (l - ii + 1)) {
+    base += l - ii + 1;
+    --ii;
+  }
+  int kk = (l - ii) - (c - base);
+  i = ii;
+  k = kk;
+  m = l - ii - kk;
+}
+
+__host__ __device__ inline int hs3(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
+__host__ __device__ inline int nc2(int l) { return (l + 1) * (l + 2) / 2; }
+
+// ---------------------------------------------------------------------------
+// E_t^{ij} (and F_t^{ij} = dE_t^{ij}/dAB_x) along one direction by the
+// recursions of Eqs. (Erec0)-(Erect) (with the stray "E_0" of (Erecj) read as
+// a typo) and their AB-derivatives:
+//   E_0^{00} = exp(-(ab/p) AB^2),       F_0^{00} = -(2ab/p) AB E_0^{00}
+//   E_0^{i+1,j} = -(b/p) AB E_0^{ij} + E_1^{ij}
+//   F_0^{i+1,j} = -(b/p) AB F_0^{ij} + F_1^{ij} - (b/p) E_0^{ij}
+//   E_0^{i,j+1} =  (a/p) AB E_0^{ij} + E_1^{ij}
+//   F_0^{i,j+1} =  (a/p) AB F_0^{ij} + F_1^{ij} + (a/p) E_0^{ij}
+//   E_t^{ij} = (i E_{t-1}^{i-1,j} + j E_{t-1}^{i,j-1}) / (2 p t), same for F.
+// Layout E[(i * (lb+1) + j) * (la+lb+1) + t].
+// ---------------------------------------------------------------------------
+
+__device__ inline void e_table(double a, double b, double AB, int la, int lb, double *E, double *Fd) {
+  const int nj = lb + 1, ntt = la + lb + 1;
+#define EI(i, j, t) (((i) * nj + (j)) * ntt + (t))
+  const int ne = (la + 1) * nj * ntt;
+  for (int k = 0; k < ne; ++k) {
+    E[k] = 0.0;
+    if (Fd) Fd[k] = 0.0;
+  }
+  const double p = a + b;
+  const double mu = a * b / p;
+  const double i2p = 0.5 / p;
+  E[EI(0, 0, 0)] = exp(-mu * AB * AB);
+  if (Fd) Fd[EI(0, 0, 0)] = -2.0 * mu * AB * E[EI(0, 0, 0)];
+  for (int N = 1; N <= la + lb; ++N) {
+    for (int i = (N - lb > 0 ? N - lb : 0); i <= (la < N ? la : N); ++i) {
+      const int j = N - i;
+      for (int t = 1; t <= N; ++t) {
+        double v = 0.0, w = 0.0;
+        if (i > 0) {
+          v += i * E[EI(i - 1, j, t - 1)];
+          if (Fd) w += i * Fd[EI(i - 1, j, t - 1)];
+        }
+        if (j > 0) {
+          v += j * E[EI(i, j - 1, t - 1)];
+          if (Fd) w += j * Fd[EI(i, j - 1, t - 1)];
+        }
+        E[EI(i, j, t)] = v * i2p / t;
+        if (Fd) Fd[EI(i, j, t)] = w * i2p / t;
+      }
+      if (i > 0) {
+        const double c = -(b / p) * AB;
+        E[EI(i, j, 0)] = c * E[EI(i - 1, j, 0)] + E[EI(i - 1, j, 1)];
+        if (Fd)
+          Fd[EI(i, j, 0)] = c * Fd[EI(i - 1, j, 0)] + Fd[EI(i - 1, j, 1)] -
+                              (b / p) * E[EI(i - 1, j, 0)];
+      } else {
+        const double c = (a / p) * AB;
+        E[EI(i, j, 0)] = c * E[EI(i, j - 1, 0)] + E[EI(i, j - 1, 1)];
+        if (Fd)
+          Fd[EI(i, j, 0)] = c * Fd[EI(i, j - 1, 0)] + Fd[EI(i, j - 1, 1)] +
+                              (a / p) * E[EI(i, j - 1, 0)];
+      }
+    }
+  }
+}
+#undef EI
+
+__device__ __forceinline__ void group_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+struct ContractArgs {
+  PairsDev bra, ket;
+  const int64_t *qb, *qk, *qoff, *qprim;
+  int64_t qa, p0, np;
+  const double *A;
+  int la, lb, lc, ld, i5, sw;
+  double *out;
+  int64_t out_base;
+};
+
+// Position of one-centre component (fx, fy, fz) among |f| = l_c .. l_c+l_d.
+__device__ __forceinline__ int findex(int fx, int fy, int fz, int lc) {
+  const int n = fx + fy + fz, s = fy + fz;
+  return hs3(n - 1) - hs3(lc - 1) + s * (s + 1) / 2 + fz;
+}
+
+__device__ __forceinline__ int binom3(int d, int k) {
+  return (k == 0 || k == d) ? 1 : (d == 2 ? 2 : 3);
+}
+
+__device__ __forceinline__ double ipow(double x, int n) {
+  double r = 1.0;
+  for (int i = 0; i < n; ++i) r *= x;
+  return r;
+}
+
+// Division of small non-negative ints by a per-launch constant d without the
+// integer-division sequence: q = (n * ceil(2^32/d)) >> 32 is exact while
+// n * d < 2^32 (task indices here stay below 2^20, divisors below 2^10).
+struct FastDiv {
+  uint64_t m;
+  int d;
+  __device__ __forceinline__ void init(int dd) {
+    d = dd;
+    m = ((1ull << 32) + (uint64_t)dd - 1) / (uint64_t)dd;
+  }
+  __device__ __forceinline__ int div(int n) const { return (int)(((uint64_t)n * m) >> 32); }
+};
+
+// Ket one-centre E^f_phi, f <= Lcd, at E[f(f+1)/2 + phi].
+__device__ inline void e_onecentre(double q, double XQC, int Lcd, double *E) {
+  const double i2q = 0.5 / q;
+  E[0] = 1.0;
+  for (int f = 0; f < Lcd; ++f) {
+    const double *e = E + f * (f + 1) / 2;
+    double *en = E + (f + 1) * (f + 2) / 2;
+    for (int ph = 0; ph <= f + 1; ++ph) {
+      double v = 0.0;
+      if (ph > 0) v += i2q * e[ph - 1];
+      if (ph <= f) v += XQC * e[ph];
+      if (ph + 1 <= f) v += (ph + 1) * e[ph + 1];
+      en[ph] = v;
+    }
+  }
+}
+
+// (ab|f) -> (ab|cd) by x_D^d = sum_k C(d,k) (C_x - D_x)^(d-k) x_C^k (and y, z),
+// then the store of the contracted block; U[ab * nf + f] in LDS.
+__device__ inline void hrr_store(const double *U, int la, int lb, int lc, int ld, int nf,
+                                 const double CD[3], double *out, int tid, int nt) {
+  const int nd = ncart(ld), ncd = ncart(lc) * nd;
+  const int nab = ncart(la) * ncart(lb);
+  for (int e = tid; e < nab * ncd; e += nt) {
+    const int ab = e / ncd, cd = e - ab * ncd;
+    int cx, cy, cz, dx, dy, dz;
+    cart_comp(lc, cd / nd, cx, cy, cz);
+    cart_comp(ld, cd % nd, dx, dy, dz);
+    const double *u = U + ab * nf;
+    double s = 0.0;
+    for (int kx = 0; kx <= dx; ++kx) {
+      const double wx = binom3(dx, kx) * ipow(CD[0], dx - kx);
+      for (int ky = 0; ky <= dy; ++ky) {
+        const double wy = wx * binom3(dy, ky) * ipow(CD[1], dy - ky);
+        for (int kz = 0; kz <= dz; ++kz) {
+          const double wz = wy * binom3(dz, kz) * ipow(CD[2], dz - kz);
+          s = fma(wz, u[findex(cx + kx, cy + ky, cz + kz, lc)], s);
+        }
+      }
+    }
+    out[e] = s;
+  }
+}
+
+}  // namespace f12

@@ -1,0 +1,98 @@
+"""Writes the stored expected values used by the GPU parity tests.
+
+Every value here comes from the CPU oracle (oracle/) on inputs from synth/;
+nothing is read from the GPU library.  Run from the repository root:
+
+    python tests/golden/make_golden.py [name ...]
+
+Sets:
+  df3      3 atoms (seed 77, 4 bohr cube, min. separation 1 bohr), s p d f
+           shells with 1-2 primitives, exponents log-uniform in [0.1, 10];
+           quartets that span every contraction path (same-centre (ff|ff)
+           with R = 0, multi-centre (ff|ff), (dd|dd), mixed l, (ss|ff) and
+           (ff|ss)), classes I1-I6 with the factor set P1.
+  plain20  quartets sampled from the 20-atom molecule (seed 5070), stratified
+           by total angular momentum, restricted to at most 64 primitive
+           quartets so that the oracle finishes; classes I2-I6, P1.
+"""
+import os
+import sys
+from multiprocessing import Pool
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import integrals  # noqa: E402
+from synth import FACTOR_SETS, config_plain, molecule  # noqa: E402
+
+P1 = FACTOR_SETS["P1"]
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def df3_shells():
+    return molecule(77, 3, 4.0, 1.0, (0, 1, 2, 3), 1, 2, 0.1, 10.0)[1]
+
+
+# shells: atom k holds s=4k, p=4k+1, d=4k+2, f=4k+3
+DF3_QUADS = [(3, 3, 3, 3), (7, 3, 11, 3), (6, 2, 10, 6), (3, 2, 7, 5), (0, 0, 7, 11), (11, 7, 0, 4),
+             (9, 3, 2, 8), (10, 1, 4, 7), (5, 0, 9, 4), (6, 5, 2, 9), (7, 7, 6, 10), (1, 1, 1, 1)]
+DF3_QUADS_I5 = [(3, 2, 6, 5), (2, 3, 6, 5), (7, 11, 1, 0), (0, 0, 11, 7), (6, 2, 10, 6), (5, 1, 9, 5),
+                (2, 2, 9, 4)]
+
+
+def plain20_quads(n_per_L=3, max_prim=64, seed=99):
+    _, shells = config_plain()
+    ls = np.array([s.l for s in shells])
+    ks = np.array([len(s.exps) for s in shells])
+    rng = np.random.default_rng(seed)
+    by_L = {}
+    ns = len(shells)
+    tries = 0
+    while tries < 200000 and sum(len(v) for v in by_L.values()) < 13 * n_per_L:
+        tries += 1
+        a, b, c, d = (int(x) for x in rng.integers(0, ns, 4))
+        if b > a:
+            a, b = b, a
+        if d > c:
+            c, d = d, c
+        if a * (a + 1) // 2 + b < c * (c + 1) // 2 + d:
+            a, b, c, d = c, d, a, b
+        if ks[a] * ks[b] * ks[c] * ks[d] > max_prim:
+            continue
+        L = int(ls[a] + ls[b] + ls[c] + ls[d])
+        lst = by_L.setdefault(L, [])
+        if len(lst) < n_per_L and (a, b, c, d) not in lst:
+            lst.append((a, b, c, d))
+    return [q for L in sorted(by_L) for q in by_L[L]]
+
+
+def _job(args):
+    setname, cls, quad = args
+    shells = df3_shells() if setname == "df3" else config_plain()[1]
+    sh = [shells[i].as_dict() for i in quad]
+    return args, np.asarray(integrals.contracted(cls, *sh, P1, P1), dtype=np.float64).ravel()
+
+
+def build(setname):
+    if setname == "df3":
+        jobs = [(setname, c, q) for c in (1, 2, 3, 4, 6) for q in DF3_QUADS]
+        jobs += [(setname, 5, q) for q in DF3_QUADS_I5]
+        jobs += [(setname, 3, q) for q in DF3_QUADS_I5 if q not in DF3_QUADS]
+    else:
+        quads = plain20_quads()
+        jobs = [(setname, c, q) for c in (2, 3, 4, 6) for q in quads]
+        q5 = [q for q in quads if sum(1 for _ in q) == 4][: len(quads)]
+        jobs += [(setname, 5, q) for q in q5]
+    out = {}
+    with Pool(int(os.environ.get("GOLDEN_PROCS", "6"))) as pool:
+        for (sname, cls, quad), val in pool.imap_unordered(_job, jobs):
+            out["c%d_%d_%d_%d_%d" % ((cls,) + tuple(quad))] = val
+            print(sname, cls, quad, flush=True)
+    np.savez_compressed(os.path.join(HERE, setname + ".npz"), **out)
+
+
+if __name__ == "__main__":
+    for name in (sys.argv[1:] or ["df3", "plain20"]):
+        build(name)

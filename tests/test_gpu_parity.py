@@ -129,3 +129,41 @@ def test_tiny_blocks_vs_oracle(lib, cls):
             e = block_rel_err(got[qd], ref)
         print(f"  {qd} err {e:.2e}", flush=True)
         assert e < 1e-12, (qd, e)
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name + ".npz")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def _check_golden_set(lib, shells, golden, cls, quads):
+    basis = lib.Basis.from_shells(shells)
+    pairs = lib.Pairs(basis, 1)
+    k = lib.Kernel(cls, P1, P1)
+    print(f"golden cls={cls} nquads={len(quads)}", flush=True)
+    got = run_quads(lib, basis, pairs, k, cls, quads)
+    worst = 0.0
+    for qd in quads:
+        ref = golden["c%d_%d_%d_%d_%d" % ((cls,) + tuple(qd))]
+        if cls == 5:
+            ref3 = golden["c3_%d_%d_%d_%d" % tuple(qd)]
+            bra_exps = np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps])
+            e = i5_block_err(got[qd], ref, ref3, bra_exps)
+        else:
+            e = block_rel_err(got[qd], ref)
+        worst = max(worst, e)
+        print(f"  {qd} l={[shells[i].l for i in qd]} err {e:.2e}", flush=True)
+        assert e < 1e-12, (qd, e)
+    return worst
+
+
+@pytest.mark.parametrize("cls", [1, 2, 3, 4, 6, 5])
+def test_df_blocks_vs_golden(lib, cls):
+    """s-f shells: every contraction path (small-class and large-class
+    launches, same-centre R = 0, mixed l on both sides)."""
+    sys.path.insert(0, __import__("os").path.join(__import__("os").path.dirname(__file__), "golden"))
+    from make_golden import DF3_QUADS, DF3_QUADS_I5, df3_shells
+    quads = DF3_QUADS_I5 if cls == 5 else DF3_QUADS
+    _check_golden_set(lib, df3_shells(), _golden("df3"), cls, quads)
