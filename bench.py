@@ -1,0 +1,340 @@
+"""Throughput of the F12 integral path on one MI355X.
+
+One step evaluates one batch of the 20-atom molecule's unique shell quartets
+(seed 5070; per atom s, s, p, p, d, f shells with 1-6 primitives, exponents
+log-uniform in [0.05, 50]; factor set P1) for every class I2-I6: radial
+derivatives of the basic integrals, Hermite integrals, E.R.E contraction,
+contracted blocks written to an HBM ring buffer.  The quartet list of each
+class is split into --batches stratified batches (the b-th slice of every
+(l_a, l_b, l_c, l_d) group), so successive steps cover different quartets and
+--batches steps cover the whole job.  Inputs are resident in HBM before the
+timed region.
+
+Prints one JSON line: contracted quartets/s over the timed steps (all
+classes), per-class rates, a roofline entry for the contraction kernel with
+the largest share of the time (algorithmic FP64 flops per launch over its
+launch time, both measured here with HIP events on the launch stream), and
+the CPU oracle's rate on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 flop/clk)
+CLASSES = (2, 3, 4, 5, 6)
+METRIC = "contracted shell-quartets/s per F12 class at ≤1e-12 rel err; % FP64 peak"
+
+
+# ---------------------------------------------------------------------------
+# algorithmic work per launch (FP64 flops the method must perform)
+# ---------------------------------------------------------------------------
+def _hs3(L):
+    return (L + 1) * (L + 2) * (L + 3) // 6 if L >= 0 else 0
+
+
+def _nc(l):
+    return (l + 1) * (l + 2) // 2
+
+
+def _carts(l):
+    return [(i, k, l - i - k) for i in range(l, -1, -1) for k in range(l - i, -1, -1)]
+
+
+def _ket_fmas(Lab, lc, Lcd):
+    """FMAs of the three one-dimensional ket passes for one primitive quartet."""
+    z = 0
+    for v in range(Lab + 1):
+        for fz in range(Lcd + 1):
+            m = Lab - v + Lcd - fz
+            z += (m + 1) * (m + 2) // 2 * (fz + 1)
+    y = 0
+    for u in range(Lab + 1):
+        for v in range(Lab + 1 - u):
+            for fy in range(Lcd + 1):
+                for fz in range(Lcd + 1 - fy):
+                    y += (Lab - u - v + Lcd - fy - fz + 1) * (fy + 1)
+    x = 0
+    for t in range(Lab + 1):
+        for u in range(Lab + 1 - t):
+            for v in range(Lab + 1 - t - u):
+                for f in range(lc, Lcd + 1):
+                    for (fx, _, _) in _carts(f):
+                        x += fx + 1
+    return z + y + x
+
+
+def _bra_fmas(la, Lab, nf):
+    """FMAs of a factorised bra transform for one bra primitive."""
+    x = sum(ex + 1 for ex in range(Lab + 1) for u in range(Lab + 1) for v in range(Lab + 1 - u)
+            if u + v <= Lab - ex)
+    y = sum(ey + 1 for ex in range(Lab + 1) for ey in range(Lab + 1 - ex) for v in range(Lab + 1 - ex - ey))
+    z = sum(ez + 1 for e in range(la, Lab + 1) for (_, _, ez) in _carts(e))
+    return (x + y + z) * nf
+
+
+def _hrr_fmas(la, lb, lc, ld):
+    n = 0
+    for (dx, dy, dz) in _carts(ld):
+        n += (dx + 1) * (dy + 1) * (dz + 1)
+    return n * _nc(la) * _nc(lb) * _nc(lc)
+
+
+def contraction_flops(la, lb, lc, ld, i5, n_prim, n_bra_prim, n_quartets):
+    """Algorithmic FP64 flops of one contraction launch: R recursion, ket
+    passes, bra transform, transfer to (cd); I5 runs four components."""
+    Lab, Lcd = la + lb, lc + ld
+    L = Lab + Lcd + (2 if i5 else 0)
+    ncomp = 4 if i5 else 1
+    nf = _hs3(Lcd) - _hs3(lc - 1)
+    r = sum(_hs3(L - n) for n in range(L + 1))
+    per_prim = 2 * r + ncomp * 2 * _ket_fmas(Lab, lc, Lcd) + (2 * _hs3(Lab + Lcd) if i5 else 0)
+    per_bra = ncomp * 2 * _bra_fmas(la, Lab, nf)
+    return per_prim * n_prim + per_bra * n_bra_prim + 2 * _hrr_fmas(la, lb, lc, ld) * n_quartets
+
+
+def kernel_name(la, lb, lc, ld, i5):
+    Lab, Lcd = la + lb, lc + ld
+    if Lab + Lcd + (2 if i5 else 0) > 4:
+        return "big_kernel<%d, %d, %s>" % (Lab, Lcd, "true" if i5 else "false")
+    return "contract_kernel<L=%d%s>" % (Lab + Lcd, ", I5" if i5 else "")
+
+
+# ---------------------------------------------------------------------------
+# CPU oracle on a bounded sample
+# ---------------------------------------------------------------------------
+def cpu_baseline(shells, quads, budget_s=20.0, seed=7):
+    """I3 oracle rate: quartets drawn uniformly from the I3 list among those
+    with at most 4 primitive quartets, evaluated until the time budget is
+    used; each quartet's time is scaled linearly to the list's mean
+    primitive count (the oracle's cost grows about linearly with it)."""
+    from oracle import integrals
+    from synth import FACTOR_SETS
+    P1 = FACTOR_SETS["P1"]
+    ks = np.array([len(s.exps) for s in shells])
+    pq = ks[quads].prod(axis=1)
+    pbar = float(pq.mean())
+    cand = np.nonzero(pq <= 4)[0]
+    rng = np.random.default_rng(seed)
+    t_scaled, used, n = 0.0, 0.0, 0
+    while used < budget_s or n < 3:
+        pick = int(rng.choice(cand))
+        sh = [shells[i].as_dict() for i in quads[pick]]
+        t0 = time.perf_counter()
+        integrals.contracted(3, *sh, P1, P1)
+        dt = time.perf_counter() - t0
+        used += dt
+        t_scaled += dt * pbar / float(pq[pick])
+        n += 1
+    return n / t_scaled, used, n
+
+
+# ---------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batches", type=int, default=16)
+    ap.add_argument("--classes", default=",".join(str(c) for c in CLASSES))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the integral path has no multi-GPU mode; use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1412_5070_amd import f12int
+    from synth import FACTOR_SETS, config_plain
+
+    t_start = time.perf_counter()
+
+    def log(msg):
+        print("[bench %7.1fs] %s" % (time.perf_counter() - t_start, msg), file=sys.stderr, flush=True)
+
+    classes = [int(c) for c in args.classes.split(",")]
+    P1 = FACTOR_SETS["P1"]
+    _, shells = config_plain()
+    ls = np.array([s.l for s in shells])
+    ks = np.array([len(s.exps) for s in shells])
+    basis = f12int.Basis.from_shells(shells)
+    pairs = f12int.Pairs(basis, 0)
+    stream = torch.cuda.current_stream()
+
+    # per class: quartet list, kernel, slices of every (la,lb,lc,ld) group
+    work = []
+    for cls in classes:
+        kern = f12int.Kernel(cls, P1, P1)
+        Q = f12int.Quartets.build(pairs, pairs, cls)
+        quads = Q.quads()
+        offs = Q.offsets()
+        key = ((ls[quads[:, 0]] * 4 + ls[quads[:, 1]]) * 4 + ls[quads[:, 2]]) * 4 + ls[quads[:, 3]]
+        starts = np.concatenate([[0], np.nonzero(np.diff(key))[0] + 1, [len(key)]])
+        nprim = ks[quads].prod(axis=1).astype(np.int64)
+        nbra = (ks[quads[:, 0]] * ks[quads[:, 1]]).astype(np.int64)
+        cprim = np.concatenate([[0], np.cumsum(nprim)])
+        cbra = np.concatenate([[0], np.cumsum(nbra)])
+        cap = f12int.scratch_prims(Q)
+        groups = []
+        for g in range(len(starts) - 1):
+            a, b = int(starts[g]), int(starts[g + 1])
+            la, lb, lc, ld = (int(ls[quads[a, i]]) for i in range(4))
+            groups.append((a, b, (la, lb, lc, ld)))
+        work.append(dict(cls=cls, kern=kern, Q=Q, offs=offs, groups=groups, cprim=cprim, cbra=cbra,
+                         cap=cap, nq=len(key), quads=quads if cls == 3 else None))
+        log("I%d: %d quartets in %d groups" % (cls, len(key), len(groups)))
+
+    ring = torch.empty(1 << 28, dtype=torch.float64, device="cuda")  # 2 GiB output ring
+    ring_pos = [0]
+
+    def slices(wk, batch):
+        for (a, b, lq) in wk["groups"]:
+            n = b - a
+            s0 = a + (n * batch) // args.batches
+            s1 = a + (n * (batch + 1)) // args.batches
+            while s0 < s1:
+                # split so that a slice's primitive quartets fit the scratch
+                hi = int(np.searchsorted(wk["cprim"], wk["cprim"][s0] + wk["cap"], side="right")) - 1
+                e = max(s0 + 1, min(s1, hi))
+                yield s0, e, lq
+                s0 = e
+
+    def run_step(batch, record):
+        for wk in work:
+            Q, kern, offs = wk["Q"], wk["kern"], wk["offs"]
+            ev_cls0 = torch.cuda.Event(enable_timing=True)
+            ev_cls1 = torch.cuda.Event(enable_timing=True)
+            ev_cls0.record(stream)
+            nq = 0
+            for (s0, s1, lq) in slices(wk, batch):
+                size = int(offs[s1] - offs[s0])
+                if ring_pos[0] + size > ring.numel():
+                    ring_pos[0] = 0
+                out = ring[ring_pos[0]:ring_pos[0] + size]
+                ring_pos[0] += size
+                ea = torch.cuda.Event(enable_timing=True)
+                ea.record(stream)
+                f12int.eval_stage(Q, kern, out, s0, s1, 1, stream)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                f12int.eval_stage(Q, kern, out, s0, s1, 2, stream)
+                e1.record(stream)
+                if record is not None:
+                    record["aux"].append((ea, e0))
+                nq += s1 - s0
+                if record is not None:
+                    la, lb, lc, ld = lq
+                    i5 = wk["cls"] == 5
+                    fl = contraction_flops(la, lb, lc, ld, i5, int(wk["cprim"][s1] - wk["cprim"][s0]),
+                                           int(wk["cbra"][s1] - wk["cbra"][s0]), s1 - s0)
+                    record["launches"].append((kernel_name(la, lb, lc, ld, i5), fl, e0, e1))
+            ev_cls1.record(stream)
+            if record is not None:
+                record["classes"].append((wk["cls"], nq, ev_cls0, ev_cls1))
+            torch.cuda.synchronize()
+            log("batch %d I%d: %d quartets done" % (batch, wk["cls"], nq))
+
+    for w in range(args.warmup):
+        run_step(w % args.batches, None)
+    torch.cuda.synchronize()
+    f12int.stream_status()
+    rec = {"launches": [], "classes": [], "aux": []}
+    t0 = time.perf_counter()
+    nq_total = 0
+    for s in range(args.steps):
+        batch = (args.warmup + s) % args.batches
+        run_step(batch, rec)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    f12int.stream_status()
+    nq_total = sum(n for (_, n, _, _) in rec["classes"])
+
+    per_class = {}
+    for (cls, n, e0, e1) in rec["classes"]:
+        d = per_class.setdefault("I%d" % cls, [0, 0.0])
+        d[0] += n
+        d[1] += e0.elapsed_time(e1) / 1e3
+    per_class_rate = {k: v[0] / v[1] for k, v in per_class.items()}
+
+    by_kernel = {}
+    for (name, fl, e0, e1) in rec["launches"]:
+        d = by_kernel.setdefault(name, [0, 0.0, 0.0])
+        d[0] += 1
+        d[1] += fl
+        d[2] += e0.elapsed_time(e1) / 1e3
+    dom = max(by_kernel, key=lambda k: by_kernel[k][2])
+    n_c = sum(v[0] for v in by_kernel.values())
+    fl_c = sum(v[1] for v in by_kernel.values())
+    contraction_time = sum(v[2] for v in by_kernel.values())
+    achieved = fl_c / contraction_time / 1e12
+    aux_time = sum(a.elapsed_time(b) / 1e3 for (a, b) in rec["aux"])
+    gpu_time = sum(v[1] for v in per_class.values())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        wk3 = [wk for wk in work if wk["cls"] == 3]
+        if wk3:
+            log("CPU oracle sample")
+            rate, used, nsamp = cpu_baseline(shells, wk3[0]["quads"])
+            log("CPU oracle: %.3g quartets/s" % rate)
+            cpu = {"value": rate, "unit": "quartets/s", "cores": 1, "kind": "oracle",
+                   "sample": "I3: %d quartets drawn uniformly from the 20-atom list among those with "
+                             "<= 4 primitive quartets, each time scaled to the list's mean primitive "
+                             "count; %.1f s of CPU work on one core" % (nsamp, used)}
+
+    line = {
+        "metric": METRIC,
+        "value": nq_total / elapsed,
+        "unit": "quartets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "20 atoms in a 12 bohr cube (seed 5070), s,s,p,p,d,f shells with 1-6 "
+                        "primitives, all unique quartets of I2-I6 (factor P1), one of %d stratified "
+                        "batches per step" % args.batches,
+            "classes": ["I%d" % c for c in classes],
+            "quartets_per_step": nq_total // max(args.steps, 1),
+        },
+        "per_class_quartets_per_s": per_class_rate,
+        "roofline": {
+            "kernel": "E.R.E contraction (big_kernel<*>, contract_kernel<*>)",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "launches": n_c,
+            "avg_launch_ms": contraction_time / n_c * 1e3,
+            "flops_per_launch": fl_c / n_c,
+            "share_of_gpu_time": contraction_time / gpu_time,
+            "largest_instantiation": {
+                "kernel": dom, "launches": by_kernel[dom][0],
+                "avg_launch_ms": by_kernel[dom][2] / by_kernel[dom][0] * 1e3,
+                "achieved": by_kernel[dom][1] / by_kernel[dom][2] / 1e12},
+            "aux_kernel": {"launches": len(rec["aux"]), "avg_launch_ms": aux_time / max(len(rec["aux"]), 1) * 1e3,
+                           "share_of_gpu_time": aux_time / gpu_time},
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,20 @@ void f12_quartets_destroy(f12_quartets *q);
 int f12_eval(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
              double *d_out, int64_t out_capacity, void *stream);
 
+/* The two launches of f12_eval, separately, for timing them one by one.
+ * [q_begin, q_end) must lie inside one (l_a, l_b, l_c, l_d) group of the
+ * public order and hold at most f12_quartets_scratch_prims primitive
+ * quartets (else F12_EBUFSIZE).  stage 1 enqueues the radial derivatives
+ * A_n (Eq. (bfinal), D^n) into the list's scratch; stage 2 enqueues the
+ * Hermite integrals and the E.R.E contraction (Eq. (ri), Eq. (ii)) of the
+ * same range with the same kernel, writing d_out as f12_eval does (F12_EINVAL
+ * if stage 1 of that range and kernel did not come first).  Together they
+ * give the same result as f12_eval on the range. */
+int f12_eval_stage(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
+                   double *d_out, int64_t out_capacity, int32_t stage, void *stream);
+/* Primitive quartets the list's scratch holds (bound for f12_eval_stage). */
+int f12_quartets_scratch_prims(const f12_quartets *q, int64_t *n_prim_quartets);
+
 /* ------------------------------------------------------------ diagnostics -- */
 /* Radial derivatives A_n = (R^-1 d/dR)^n B_i (Eq. (bfinal), n = 0..L) of the
  * kernel's basic integral, computed by the same device code as f12_eval,

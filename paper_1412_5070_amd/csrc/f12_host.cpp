@@ -131,6 +131,9 @@ struct f12_quartets {
   DevBuf<int64_t> d_qb, d_qk, d_qoff, d_qprim;
   DevBuf<double> d_A;
   int64_t a_cap_prims = 0;
+  // range whose radial derivatives sit in d_A after f12_eval_stage(stage 1)
+  int64_t stage_qa = -1, stage_qe = -1;
+  const f12_kernel *stage_k = nullptr;
 };
 
 // ============================================================================
@@ -960,5 +963,46 @@ extern "C" int f12_eval(f12_quartets *q, const f12_kernel *k, int64_t q_begin, i
   if (k->cls != q->cls) return F12_EINVAL;
   if (q->qoff[q_end] - q->qoff[q_begin] > out_capacity) return F12_EBUFSIZE;
   if (q_begin == q_end) return F12_OK;
+  q->stage_qa = q->stage_qe = -1;
   return eval_range(q, k, q_begin, q_end, d_out, (hipStream_t)stream);
+}
+
+extern "C" int f12_eval_stage(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
+                              double *d_out, int64_t out_capacity, int32_t stage, void *stream) {
+  if (!q || !k || q_begin < 0 || q_end > q->nq || q_begin >= q_end) return F12_EINVAL;
+  if (k->cls != q->cls || (stage != 1 && stage != 2)) return F12_EINVAL;
+  const Bin *bin = nullptr;
+  for (const Bin &b : q->bins)
+    if (q_begin >= b.q0 && q_begin < b.q0 + b.nq) bin = &b;
+  if (!bin || q_end > bin->q0 + bin->nq) return F12_EINVAL;
+  const int64_t p0 = q->qprim[q_begin], np = q->qprim[q_end] - p0;
+  if (np > q->a_cap_prims) return F12_EBUFSIZE;
+  const PairsDev bra = q->bra->dev(), ket = q->ket->dev();
+  const int i5 = (q->cls == 5);
+  hipStream_t st = (hipStream_t)stream;
+  if (stage == 1) {
+    const int L = bin->la + bin->lb + bin->lc + bin->ld + (i5 ? 2 : 0);
+    if (launch_aux(k->d_desc.ptr, bra, ket, q->d_qb.ptr, q->d_qk.ptr, q->d_qprim.ptr, q_begin,
+                   q_end - q_begin, p0, np, L, q->d_A.ptr, st) != 0)
+      return F12_EDEVICE;
+    q->stage_qa = q_begin;
+    q->stage_qe = q_end;
+    q->stage_k = k;
+    return F12_OK;
+  }
+  if (!d_out) return F12_EINVAL;
+  if (q->stage_qa != q_begin || q->stage_qe != q_end || q->stage_k != k) return F12_EINVAL;
+  if (q->qoff[q_end] - q->qoff[q_begin] > out_capacity) return F12_EBUFSIZE;
+  q->stage_qa = q->stage_qe = -1;
+  if (launch_contract(bra, ket, q->d_qb.ptr, q->d_qk.ptr, q->d_qoff.ptr, q->d_qprim.ptr, q_begin,
+                      q_end - q_begin, p0, np, q->d_A.ptr, bin->la, bin->lb, bin->lc, bin->ld, i5,
+                      d_out, q->qoff[q_begin], st) != 0)
+    return F12_EDEVICE;
+  return F12_OK;
+}
+
+extern "C" int f12_quartets_scratch_prims(const f12_quartets *q, int64_t *n) {
+  if (!q || !n) return F12_EINVAL;
+  *n = q->a_cap_prims;
+  return F12_OK;
 }

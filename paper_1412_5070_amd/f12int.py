@@ -53,6 +53,8 @@ EXPORTS = {
     "f12_quartets_prim_count": (_c_i32, [_vp, _P(_c_i64)]),
     "f12_quartets_destroy": (None, [_vp]),
     "f12_eval": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp]),
+    "f12_eval_stage": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i32, _vp]),
+    "f12_quartets_scratch_prims": (_c_i32, [_vp, _P(_c_i64)]),
     "f12_aux_radial": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _c_i32, _c_i32, _vp, _vp]),
     "f12_aux_w_column": (_c_i32, [_c_dbl, _c_i32, _c_i32, _c_i32, _c_dbl, _P(_c_dbl)]),
     "f12_stream_status": (_c_i32, [_vp]),
@@ -209,6 +211,23 @@ def eval_into(quartets, kernel, out, q_begin=0, q_end=None, stream=None):
     _check(_lib.f12_eval(quartets.handle, kernel.handle, int(q_begin), int(q_end), _vp(out.data_ptr()),
                          out.numel(), _stream_ptr(stream)), "f12_eval")
     return out
+
+
+def eval_stage(quartets, kernel, out, q_begin, q_end, stage, stream=None):
+    """Enqueue one launch of f12_eval (stage 1: radial derivatives, stage 2:
+    contraction) for a range inside one angular-momentum group."""
+    import torch
+    assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+    _check(_lib.f12_eval_stage(quartets.handle, kernel.handle, int(q_begin), int(q_end),
+                               _vp(out.data_ptr()), out.numel(), int(stage), _stream_ptr(stream)),
+           "f12_eval_stage")
+    return out
+
+
+def scratch_prims(quartets):
+    n = _c_i64()
+    _check(_lib.f12_quartets_scratch_prims(quartets.handle, ctypes.byref(n)), "f12_quartets_scratch_prims")
+    return int(n.value)
 
 
 def stream_status(stream=None):
