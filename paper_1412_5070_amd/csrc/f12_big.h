@@ -16,7 +16,14 @@
 // primitive the bra transform I[ab][f] += c_a c_b sum_h (-1)^{|h|} E^ab_h V[h][f]
 // (Eq. (ii)) accumulates in registers, and the exponent-free transfer
 // x_D^d = sum_k C(d,k) (C_x - D_x)^(d-k) x_C^k gives (ab|cd) at the end.
-// I5 (Eq. (I5byI3_) with gradient coefficient -1):
+// I5 has two forms.  MODE 2 (the default where LDS and registers allow):
+// I5 = 1/2 (lap_A - lap_B) I3 (Eq. (I5_)) with the one-dimensional Laplacian
+// of x_A^i exp(-a x_A^2), i(i-1) x^(i-2) - 2a(2i+1) x^i + 4a^2 x^(i+2), folded
+// into the bra coefficients: one ket transform over bra Hermite indices up to
+// l_a + l_b + 2 and, per direction d, D^{ij}_t = 1/2 [i(i-1) E^{i-2,j} -
+// 2a(2i+1) E^{ij} + 4a^2 E^{i+2,j} - j(j-1) E^{i,j-2} + 2b(2j+1) E^{ij} -
+// 4b^2 E^{i,j+2}]_t in place of E along d.  MODE 1 (Eq. (I5byI3_) with
+// gradient coefficient -1) runs four ket transforms:
 //   comp 0: (a-b)/(2p) E^ab with R_lap = R_{t+2,u,v} + R_{t,u+2,v} + R_{t,u,v+2},
 //   comp d: -F^ab_d with R shifted by one along d.
 #pragma once
@@ -49,8 +56,22 @@ constexpr int max_nf(int lcd) {
   return hs3c(lcd) - hs3c(lcmin - 1);
 }
 
-template <int LAB, int LCD, bool I5>
+// Bra E tables up to (l_a + 2, l_b + 2) and the D tables of MODE 2.
+constexpr int max_eab2(int lab) {
+  int m = 0;
+  for (int la = 0; la <= LMAX; ++la) {
+    const int lb = lab - la;
+    if (lb >= 0 && lb <= LMAX) m = cmax(m, 3 * (la + 3) * (lb + 3) * (lab + 5) + 3 * (la + 1) * (lb + 1) * (lab + 3));
+  }
+  return m;
+}
+
+// MODE: 0 = I1-I4, I6; 1 = I5 by four components; 2 = I5 by the Laplacian
+// form, with LAB = l_a + l_b + 2 (the bra Hermite range of the ket transform).
+template <int LAB, int LCD, int MODE>
 struct BigShape {
+  static constexpr bool I5 = MODE == 1;
+  static constexpr int BLAB = MODE == 2 ? LAB - 2 : LAB;  // l_a + l_b
   static constexpr int NT = 256;
   static constexpr int LP = LAB + LCD;
   static constexpr int L = LP + (I5 ? 2 : 0);
@@ -66,7 +87,7 @@ struct BigShape {
   static constexpr int YST = NUV * NE;
   static constexpr int NZT = NLP * (LAB + 1);
   static constexpr int NYT = (LP + 1) * (LAB + 1) * (LCD + 1);
-  static constexpr int NEB = (I5 ? 6 : 3) * max_eab(LAB);
+  static constexpr int NEB = MODE == 2 ? max_eab2(BLAB) : (I5 ? 6 : 3) * max_eab(LAB);
   // LDS (doubles)
   static constexpr int oRp = NEB;              // R levels (ping-pong), later R_lap lines
   static constexpr int oRl = oRp + 2 * HL;     // R lines
@@ -85,10 +106,10 @@ struct BigShape {
     return s;
   }
   static constexpr int MAXW = off_fx(LCD + 1);
-  static constexpr int MAXU = (max_nab(LAB) * max_nf(LCD) + NT - 1) / NT;
+  static constexpr int MAXU = (max_nab(BLAB) * max_nf(LCD) + NT - 1) / NT;
   static_assert(nc2c(LP) * (LP + 1) <= 2 * HL || !I5, "R_lap lines must fit the level buffers");
   static_assert(HAB * NF0 <= DBL - oRp, "V staging must fit");
-  static_assert(max_nab(LAB) * max_nf(LCD) <= DBL - oRp, "(ab|f) staging must fit");
+  static_assert(max_nab(BLAB) * max_nf(LCD) <= DBL - oRp, "(ab|f) staging must fit");
 };
 
 template <int NCOL, int STRIDE>
@@ -97,14 +118,20 @@ __device__ __forceinline__ void load_col(const double *p, int last, double (&c)[
   for (int w = 0; w < NCOL; ++w) c[w] = (w <= last) ? p[w * STRIDE] : 0.0;
 }
 
-template <int LAB, int LCD, bool I5>
+template <int LAB, int LCD, int MODE>
 __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
-  using S = BigShape<LAB, LCD, I5>;
+  using S = BigShape<LAB, LCD, MODE>;
   constexpr int NT = S::NT, LP = S::LP, L = S::L, NE = S::NE;
+  constexpr bool I5 = S::I5;
+  constexpr int BLAB = S::BLAB;
   extern __shared__ double lds[];
   const int tid = threadIdx.x;
   const int la = a.la, lb = a.lb, lc = a.lc, ld = a.ld;
-  const int Eab1 = (la + 1) * (lb + 1) * (LAB + 1);
+  // bra tables: MODE 0/1 E (and F) up to (l_a, l_b); MODE 2 E up to
+  // (l_a + 2, l_b + 2) with stride ES, then D up to (l_a, l_b) with stride DS
+  const int ESb = MODE == 2 ? lb + 3 : lb + 1, ESt = MODE == 2 ? BLAB + 5 : BLAB + 1;
+  const int Eab1 = (MODE == 2 ? la + 3 : la + 1) * ESb * ESt;
+  const int DSt = BLAB + 3, Dab1 = (la + 1) * (lb + 1) * DSt;
   double *Eb = lds, *Fb = lds + 3 * Eab1;
   double *Rp = lds + S::oRp, *Rl = lds + S::oRl, *Zb = lds + S::oZ, *Yb = lds + S::oY;
   double *Ek = lds + S::oEk;
@@ -185,7 +212,26 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
     const double ea = bra.ea[ppb], eb = bra.eb[ppb], pb = bra.p[ppb];
     const double Pb0 = bra.Px[ppb], Pb1 = bra.Py[ppb], Pb2 = bra.Pz[ppb];
     const double cab = bra.cab[ppb];
-    if (tid < 3) e_table(ea, eb, ABb[tid], la, lb, Eb + tid * Eab1, I5 ? Fb + tid * Eab1 : nullptr);
+    if (tid < 3) {
+      if constexpr (MODE == 2) {
+        const double *E = Eb + tid * Eab1;
+        double *D = Fb + tid * Dab1;
+        e_table(ea, eb, ABb[tid], la + 2, lb + 2, Eb + tid * Eab1, nullptr);
+        for (int i = 0; i <= la; ++i)
+          for (int j = 0; j <= lb; ++j)
+            for (int t = 0; t <= i + j + 2; ++t) {
+              const double e0 = E[(i * ESb + j) * ESt + t];
+              double v = (2.0 * eb * (2 * j + 1) - 2.0 * ea * (2 * i + 1)) * e0 +
+                         4.0 * ea * ea * E[((i + 2) * ESb + j) * ESt + t] -
+                         4.0 * eb * eb * E[(i * ESb + j + 2) * ESt + t];
+              if (i >= 2) v += i * (i - 1) * E[((i - 2) * ESb + j) * ESt + t];
+              if (j >= 2) v -= j * (j - 1) * E[(i * ESb + j - 2) * ESt + t];
+              D[(i * (lb + 1) + j) * DSt + t] = 0.5 * v;
+            }
+      } else {
+        e_table(ea, eb, ABb[tid], la, lb, Eb + tid * Eab1, I5 ? Fb + tid * Eab1 : nullptr);
+      }
+    }
 #pragma unroll 1
     for (int comp = 0; comp < (I5 ? 4 : 1); ++comp) {
 #pragma unroll
@@ -364,20 +410,44 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
           int ax, ay, az, bx, by, bz;
           cart_comp(la, ab / nb, ax, ay, az);
           cart_comp(lb, ab % nb, bx, by, bz);
-          const double *exr = (comp == 1 ? Fb : Eb) + (ax * (lb + 1) + bx) * (LAB + 1);
-          const double *eyr = (comp == 2 ? Fb : Eb) + Eab1 + (ay * (lb + 1) + by) * (LAB + 1);
-          const double *ezr = (comp == 3 ? Fb : Eb) + 2 * Eab1 + (az * (lb + 1) + bz) * (LAB + 1);
           double sacc = 0.0;
-          for (int t = 0; t <= ax + bx; ++t)
-            for (int u = 0; u <= ay + by; ++u) {
-              const double exy = ((t + u) & 1) ? -exr[t] * eyr[u] : exr[t] * eyr[u];
-              double sv = 0.0;
-              for (int v = 0; v <= az + bz; ++v) {
-                const double term = ezr[v] * Vs[ridx(t, u, v) * S::NF0 + f];
-                sv += (v & 1) ? -term : term;
-              }
-              sacc = fma(exy, sv, sacc);
+          if constexpr (MODE == 2) {
+            const double *er[3] = {Eb + (ax * ESb + bx) * ESt, Eb + Eab1 + (ay * ESb + by) * ESt,
+                                   Eb + 2 * Eab1 + (az * ESb + bz) * ESt};
+            const double *dr[3] = {Fb + (ax * (lb + 1) + bx) * DSt, Fb + Dab1 + (ay * (lb + 1) + by) * DSt,
+                                   Fb + 2 * Dab1 + (az * (lb + 1) + bz) * DSt};
+            for (int d = 0; d < 3; ++d) {
+              const double *exr = d == 0 ? dr[0] : er[0];
+              const double *eyr = d == 1 ? dr[1] : er[1];
+              const double *ezr = d == 2 ? dr[2] : er[2];
+              const int nx = ax + bx + (d == 0 ? 2 : 0), ny = ay + by + (d == 1 ? 2 : 0),
+                        nz = az + bz + (d == 2 ? 2 : 0);
+              for (int t = 0; t <= nx; ++t)
+                for (int u = 0; u <= ny; ++u) {
+                  const double exy = ((t + u) & 1) ? -exr[t] * eyr[u] : exr[t] * eyr[u];
+                  double sv = 0.0;
+                  for (int v = 0; v <= nz; ++v) {
+                    const double term = ezr[v] * Vs[ridx(t, u, v) * S::NF0 + f];
+                    sv += (v & 1) ? -term : term;
+                  }
+                  sacc = fma(exy, sv, sacc);
+                }
             }
+          } else {
+            const double *exr = (comp == 1 ? Fb : Eb) + (ax * (lb + 1) + bx) * (LAB + 1);
+            const double *eyr = (comp == 2 ? Fb : Eb) + Eab1 + (ay * (lb + 1) + by) * (LAB + 1);
+            const double *ezr = (comp == 3 ? Fb : Eb) + 2 * Eab1 + (az * (lb + 1) + bz) * (LAB + 1);
+            for (int t = 0; t <= ax + bx; ++t)
+              for (int u = 0; u <= ay + by; ++u) {
+                const double exy = ((t + u) & 1) ? -exr[t] * eyr[u] : exr[t] * eyr[u];
+                double sv = 0.0;
+                for (int v = 0; v <= az + bz; ++v) {
+                  const double term = ezr[v] * Vs[ridx(t, u, v) * S::NF0 + f];
+                  sv += (v & 1) ? -term : term;
+                }
+                sacc = fma(exy, sv, sacc);
+              }
+          }
           uacc[k] = fma(cw, sacc, uacc[k]);
         }
       }
@@ -394,18 +464,25 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
   hrr_store(Uf, la, lb, lc, ld, nf, CD, a.out + o, tid, NT);
 }
 
-template <int LAB, int LCD, bool I5>
+template <int LAB, int LCD, int MODE>
 inline int launch_big_t(const ContractArgs &a, unsigned nblocks, hipStream_t st) {
-  using S = BigShape<LAB, LCD, I5>;
+  using S = BigShape<LAB, LCD, MODE>;
   static bool attr = false;
   if (!attr) {
-    if (hipFuncSetAttribute((const void *)big_kernel<LAB, LCD, I5>,
+    if (hipFuncSetAttribute((const void *)big_kernel<LAB, LCD, MODE>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::BYTES) != hipSuccess)
       return -1;
     attr = true;
   }
-  hipLaunchKernelGGL((big_kernel<LAB, LCD, I5>), dim3(nblocks), dim3(256), S::BYTES, st, a);
+  hipLaunchKernelGGL((big_kernel<LAB, LCD, MODE>), dim3(nblocks), dim3(256), S::BYTES, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// The Laplacian form of I5 is used where its LDS and register slots fit.
+template <int LAB, int LCD>
+constexpr bool lap_fits() {
+  using S = BigShape<LAB + 2, LCD, 2>;
+  return S::BYTES <= 160 * 1024 && S::MAXW <= 40 && S::MAXU <= 32;
 }
 
 // Shapes handled here: L_ab + L_cd + (I5 ? 2 : 0) > 4.
@@ -416,9 +493,12 @@ inline int launch_big_lab(int lcd, int i5, const ContractArgs &a, unsigned nbloc
 #define F12_BIG_CASE(LCD)                                                              \
   case LCD:                                                                            \
     if (i5) {                                                                          \
-      if constexpr (big_shape(LAB, LCD, true)) return launch_big_t<LAB, LCD, true>(a, nblocks, st); \
+      if constexpr (big_shape(LAB, LCD, true)) {                                       \
+        if constexpr (lap_fits<LAB, LCD>()) return launch_big_t<LAB + 2, LCD, 2>(a, nblocks, st); \
+        else return launch_big_t<LAB, LCD, 1>(a, nblocks, st);                          \
+      }                                                                                \
     } else {                                                                           \
-      if constexpr (big_shape(LAB, LCD, false)) return launch_big_t<LAB, LCD, false>(a, nblocks, st); \
+      if constexpr (big_shape(LAB, LCD, false)) return launch_big_t<LAB, LCD, 0>(a, nblocks, st); \
     }                                                                                  \
     return -1;
   switch (lcd) {

@@ -39,7 +39,7 @@ def df3_shells():
 DF3_QUADS = [(3, 3, 3, 3), (7, 3, 11, 3), (6, 2, 10, 6), (3, 2, 7, 5), (0, 0, 7, 11), (11, 7, 0, 4),
              (9, 3, 2, 8), (10, 1, 4, 7), (5, 0, 9, 4), (6, 5, 2, 9), (7, 7, 6, 10), (1, 1, 1, 1)]
 DF3_QUADS_I5 = [(3, 2, 6, 5), (2, 3, 6, 5), (7, 11, 1, 0), (0, 0, 11, 7), (6, 2, 10, 6), (5, 1, 9, 5),
-                (2, 2, 9, 4)]
+                (2, 2, 9, 4), (3, 2, 7, 11)]
 
 
 def plain20_quads(n_per_L=3, max_prim=64, seed=99):
