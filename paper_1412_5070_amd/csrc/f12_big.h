@@ -68,7 +68,7 @@ constexpr int max_eab2(int lab) {
 
 // MODE: 0 = I1-I4, I6; 1 = I5 by four components; 2 = I5 by the Laplacian
 // form, with LAB = l_a + l_b + 2 (the bra Hermite range of the ket transform).
-template <int LAB, int LCD, int MODE>
+template <int LAB, int LCD, int MODE, int NJ>
 struct BigShape {
   static constexpr bool I5 = MODE == 1;
   static constexpr int BLAB = MODE == 2 ? LAB - 2 : LAB;  // l_a + l_b
@@ -89,12 +89,19 @@ struct BigShape {
   static constexpr int NYT = (LP + 1) * (LAB + 1) * (LCD + 1);
   static constexpr int NEB = MODE == 2 ? max_eab2(BLAB) : (I5 ? 6 : 3) * max_eab(LAB);
   // LDS (doubles)
-  static constexpr int oRp = NEB;              // R levels (ping-pong), later R_lap lines
-  static constexpr int oRl = oRp + 2 * HL;     // R lines
-  static constexpr int oZ = oRl + NLL * RLS;
-  static constexpr int oY = oZ + NLP * ZST;
-  static constexpr int oEk = oY + (LP + 1) * YST;
-  static constexpr int DBL = oEk + 3 * NE + 8;  // + pad: loads past a line end stay inside
+  // per ket primitive of a pass: Z, Y, one-centre E
+  static constexpr int jZ = 0;
+  static constexpr int jY = jZ + NLP * ZST;
+  static constexpr int jEk = jY + (LP + 1) * YST;
+  static constexpr int PJ = jEk + 3 * NE;
+  // ket primitives staged at a time: centre Q, q, d exponent, weight; A_0..A_L
+  static constexpr int KC = 32;
+  static constexpr int KDW = 6;
+  static constexpr int oHC = NEB;                         // c(T, i) table
+  static constexpr int oKD = oHC + (LTOT_MAX + 1) * (LTOT_MAX / 2 + 1);
+  static constexpr int oAS = oKD + KC * KDW;
+  static constexpr int oRp = oAS + KC * (L + 1);
+  static constexpr int DBL = oRp + NJ * PJ + 8;  // + pad: loads past a line end stay inside
   static constexpr int INTS = HL + NLP;
   static constexpr size_t BYTES = (size_t)DBL * 8 + (size_t)INTS * 4;
   // V slots: for each f_x, HAB * (#(fy,fz) with fy + fz <= LCD - fx) elements
@@ -107,7 +114,6 @@ struct BigShape {
   }
   static constexpr int MAXW = off_fx(LCD + 1);
   static constexpr int MAXU = (max_nab(BLAB) * max_nf(LCD) + NT - 1) / NT;
-  static_assert(nc2c(LP) * (LP + 1) <= 2 * HL || !I5, "R_lap lines must fit the level buffers");
   static_assert(HAB * NF0 <= DBL - oRp, "V staging must fit");
   static_assert(max_nab(BLAB) * max_nf(LCD) <= DBL - oRp, "(ab|f) staging must fit");
 };
@@ -118,9 +124,78 @@ __device__ __forceinline__ void load_col(const double *p, int last, double (&c)[
   for (int w = 0; w < NCOL; ++w) c[w] = (w <= last) ? p[w * STRIDE] : 0.0;
 }
 
-template <int LAB, int LCD, int MODE>
+// c(T, i) = T! / (i! (T - 2i)! 2^i): the coefficient of X^(T-2i) D^(T-i) in
+// d^T/dX^T of a function of |X|^2/2 (D = R^-1 d/dR); table [T][i], T <= 14.
+constexpr int HC_T = LTOT_MAX + 1, HC_I = LTOT_MAX / 2 + 1;
+
+// One Hermite line R_{T,U,w+SH}, w = 0..NW-1, of the primitive quartet, from
+//   R_{T,U,W} = sum_{i,j,k} c(T,i) X^(T-2i) c(U,j) Y^(U-2j) c(W,k) Z^(W-2k) A_{T+U+W-i-j-k},
+// the closed form of the recurrence R^(n)_{t+1,u,v} = t R^(n+1)_{t-1,u,v} +
+// X R^(n+1)_{tuv} (each d/dX of a radial function is X D).  Entries past the
+// line end (T + U + W > L) are 0.
+template <int L, int NW, int SH>
+__device__ __forceinline__ void r_line(int T, int U, double X, double Y, double Z, const double *A,
+                                       const double *hc, double (&R)[NW]) {
+  constexpr int H = L / 2;
+  // col[m] = sum_{i,j} c(T,i) X^(T-2i) c(U,j) Y^(U-2j) A_{(T-i)+(U-j)+m}
+  double hx[H + 1], hy[H + 1];
+  {
+    double px = (T & 1) ? X : 1.0, py = (U & 1) ? Y : 1.0;
+    const double X2 = X * X, Y2 = Y * Y;
+#pragma unroll
+    for (int i = H; i >= 0; --i) {
+      hx[i] = 0.0;
+      hy[i] = 0.0;
+      if (2 * i <= T) {
+        hx[i] = hc[T * HC_I + i] * px;
+        px *= X2;
+      }
+      if (2 * i <= U) {
+        hy[i] = hc[U * HC_I + i] * py;
+        py *= Y2;
+      }
+    }
+  }
+  const int rem = L - T - U;
+  double col[L + 1];
+#pragma unroll
+  for (int m = 0; m <= L; ++m) col[m] = 0.0;
+#pragma unroll
+  for (int i = 0; i <= H; ++i) {
+    if (2 * i > T) continue;
+#pragma unroll
+    for (int j = 0; j <= H; ++j) {
+      if (2 * j > U) continue;
+      const double w = hx[i] * hy[j];
+      const double *Ap = A + (T - i) + (U - j);
+#pragma unroll
+      for (int m = 0; m <= L; ++m)
+        if (m <= rem) col[m] = fma(w, Ap[m], col[m]);
+    }
+  }
+  double zp[L + 1];
+  zp[0] = 1.0;
+#pragma unroll
+  for (int k = 1; k <= L; ++k) zp[k] = zp[k - 1] * Z;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int W = w + SH;
+    double r = 0.0;
+    if (W <= L) {
+      double c = 1.0;  // c(W, 0)
+#pragma unroll
+      for (int k = 0; 2 * k <= W; ++k) {
+        r = fma(c * zp[W - 2 * k], col[W - k], r);
+        c = c * (W - 2 * k) * (W - 2 * k - 1) / (2.0 * (k + 1));
+      }
+    }
+    R[w] = (W <= rem) ? r : 0.0;
+  }
+}
+
+template <int LAB, int LCD, int MODE, int NJ>
 __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
-  using S = BigShape<LAB, LCD, MODE>;
+  using S = BigShape<LAB, LCD, MODE, NJ>;
   constexpr int NT = S::NT, LP = S::LP, L = S::L, NE = S::NE;
   constexpr bool I5 = S::I5;
   constexpr int BLAB = S::BLAB;
@@ -133,8 +208,6 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
   const int Eab1 = (MODE == 2 ? la + 3 : la + 1) * ESb * ESt;
   const int DSt = BLAB + 3, Dab1 = (la + 1) * (lb + 1) * DSt;
   double *Eb = lds, *Fb = lds + 3 * Eab1;
-  double *Rp = lds + S::oRp, *Rl = lds + S::oRl, *Zb = lds + S::oZ, *Yb = lds + S::oY;
-  double *Ek = lds + S::oEk;
   int *tuv = (int *)(lds + S::DBL);
   int *linetu = tuv + S::HL;
   for (int idx = tid; idx < S::HL; idx += NT) {
@@ -154,6 +227,19 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
       ++T;
     }
     linetu[line] = T | ((line - base) << 8);
+  }
+  double *hc = lds + S::oHC;
+  for (int w = tid; w < HC_T * HC_I; w += NT) {
+    const int T = w / HC_I, i = w - T * HC_I;
+    double c = 0.0;
+    if (2 * i <= T) {
+      c = 1.0;
+      for (int k = 2; k <= T; ++k) c *= k;
+      for (int k = 2; k <= i; ++k) c /= k;
+      for (int k = 2; k <= T - 2 * i; ++k) c /= k;
+      for (int k = 0; k < i; ++k) c *= 0.5;
+    }
+    hc[w] = c;
   }
   __syncthreads();
 
@@ -238,98 +324,99 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
       for (int s = 0; s < S::MAXW; ++s) wacc[s] = 0.0;
       const bool lap = I5 && comp == 0;
       const int dt = comp == 1, du = comp == 2, dv = comp == 3;
-      for (int jk = 0; jk < nket; ++jk) {
-        const int64_t ppk = ket.pp_off[kp] + jk;
+      double *KD = lds + S::oKD, *AS = lds + S::oAS;
+      for (int kc0 = 0; kc0 < nket; kc0 += S::KC) {
+      const int nkc = nket - kc0 < S::KC ? nket - kc0 : S::KC;
+      // stage the chunk's ket primitive data and radial derivatives (one
+      // round of global loads instead of one per R level)
+      for (int w = tid; w < nkc; w += NT) {
+        const int64_t ppk = ket.pp_off[kp] + kc0 + w;
         const double qk = ket.p[ppk], ed = ket.eb[ppk];
-        if (tid < 3) e_onecentre(qk, -(ed / qk) * CD[tid], LCD, Ek + tid * NE);
-        const double X0 = ket.Px[ppk] - Pb0, X1 = ket.Py[ppk] - Pb1, X2 = ket.Pz[ppk] - Pb2;
-        const double ckd = ket.cab[ppk] * exp(-(ket.ea[ppk] * ed / qk) * CD2);
-        const int64_t pl = qp0 + (int64_t)ib * nket + jk;
-        // R levels n = L..0; the last level goes to lines Rl[line(t,u)][v]
-        {
-          double *rc = Rp, *rn = Rp + S::HL;
-#pragma unroll 1
-          for (int n = L; n >= 0; --n) {
-            const int cnt = hs3(L - n);
-            for (int idx = tid; idx < cnt; idx += NT) {
-              const int code = tuv[idx];
-              const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
-              double val;
-              if (idx == 0) {
-                val = a.A[(int64_t)n * a.np + pl];
-              } else if (t > 0) {
-                val = X0 * rc[ridx(t - 1, u, v)];
-                if (t > 1) val += (t - 1) * rc[ridx(t - 2, u, v)];
-              } else if (u > 0) {
-                val = X1 * rc[ridx(t, u - 1, v)];
-                if (u > 1) val += (u - 1) * rc[ridx(t, u - 2, v)];
-              } else {
-                val = X2 * rc[ridx(t, u, v - 1)];
-                if (v > 1) val += (v - 1) * rc[ridx(t, u, v - 2)];
-              }
-              if (n == 0)
-                Rl[(t * (L + 1) - t * (t - 1) / 2 + u) * S::RLS + v] = val;
-              else
-                rn[idx] = val;
-            }
-            __syncthreads();
-            double *tmp = rc;
-            rc = rn;
-            rn = tmp;
-          }
-        }
-        if (lap) {
-          // R_lap lines over T + U <= LP, stride LP + 1, in the level buffers
-          for (int k = tid; k < S::NLP * (LP + 1); k += NT) {
-            const int line = k / (LP + 1), w = k - line * (LP + 1);
-            const int tu = linetu[line];
-            const int T = tu & 255, U = tu >> 8;
-            if (T + U + w > LP) continue;
-            const double r1 = Rl[((T + 2) * (L + 1) - (T + 2) * (T + 1) / 2 + U) * S::RLS + w];
-            const double r2 = Rl[(T * (L + 1) - T * (T - 1) / 2 + U + 2) * S::RLS + w];
-            const double r3 = Rl[(T * (L + 1) - T * (T - 1) / 2 + U) * S::RLS + w + 2];
-            Rp[line * (LP + 1) + w] = r1 + r2 + r3;
-          }
-          __syncthreads();
-        }
-        // z pass
-        {
-          double ez[NE];
+        KD[w * S::KDW + 0] = ket.Px[ppk];
+        KD[w * S::KDW + 1] = ket.Py[ppk];
+        KD[w * S::KDW + 2] = ket.Pz[ppk];
+        KD[w * S::KDW + 3] = qk;
+        KD[w * S::KDW + 4] = ed;
+        KD[w * S::KDW + 5] = ket.cab[ppk] * exp(-(ket.ea[ppk] * ed / qk) * CD2);
+      }
+      for (int w = tid; w < nkc * (L + 1); w += NT) {
+        const int j = w / (L + 1), n = w - j * (L + 1);
+        AS[w] = a.A[(int64_t)n * a.np + qp0 + (int64_t)ib * nket + kc0 + j];
+      }
+      __syncthreads();
+      for (int jk0 = 0; jk0 < nkc; jk0 += NJ) {
+        // NJ ket primitives per pass; a missing one (past the chunk) repeats
+        // jk0 with weight 0
+        double Xj0[NJ], Xj1[NJ], Xj2[NJ], ckdj[NJ];
+        int ajj[NJ];
 #pragma unroll
-          for (int k = 0; k < NE; ++k) ez[k] = Ek[2 * NE + k];
-          for (int k = tid; k < S::NZT; k += NT) {
-            const int line = k / (LAB + 1), v = k - line * (LAB + 1);
-            const int tu = linetu[line];
-            const int T = tu & 255, U = tu >> 8;
-            if (T + U + v > LP) continue;
-            const double *src;
-            int last;
-            if (lap) {
-              src = Rp + line * (LP + 1) + v;
-              last = LP - T - U - v;
-            } else {
-              const int Ts = T + dt, Us = U + du;
-              src = Rl + (Ts * (L + 1) - Ts * (Ts - 1) / 2 + Us) * S::RLS + v + dv;
-              last = L - Ts - Us - v - dv;
-            }
-            double r[LCD + 1];
-            load_col<LCD + 1, 1>(src, last, r);
-            double *zo = Zb + line * S::ZST + v * (LCD + 1);
+        for (int jj = 0; jj < NJ; ++jj) {
+          const bool ok = jk0 + jj < nkc;
+          const int jk = ok ? jk0 + jj : jk0;
+          Xj0[jj] = KD[jk * S::KDW + 0] - Pb0;
+          Xj1[jj] = KD[jk * S::KDW + 1] - Pb1;
+          Xj2[jj] = KD[jk * S::KDW + 2] - Pb2;
+          ckdj[jj] = ok ? KD[jk * S::KDW + 5] : 0.0;
+          ajj[jj] = jk * (L + 1);
+        }
+        if (tid < 3 * NJ) {
+          const int jj = tid / 3, d = tid - 3 * jj;
+          const int jk = jk0 + jj < nkc ? jk0 + jj : jk0;
+          const double qk = KD[jk * S::KDW + 3], ed = KD[jk * S::KDW + 4];
+          const double cdd = d == 0 ? CD[0] : (d == 1 ? CD[1] : CD[2]);
+          e_onecentre(qk, -(ed / qk) * cdd, LCD, lds + S::oRp + jj * S::PJ + S::jEk + d * NE);
+        }
+        // R lines from the closed form and the z pass, one (jj, line) per
+        // thread: Z[T,U][v][fz] = sum_phi E^fz_phi R_{T',U',v+phi+sh}, with
+        // (T', U', sh) = (T, U, 0), the shifted line of an I5 component, or
+        // the three terms of R_lap.
+        for (int k = tid; k < NJ * S::NLP; k += NT) {
+          const int jj = k / S::NLP, line = k - jj * S::NLP;
+          const int jk = jk0 + jj < nkc ? jk0 + jj : jk0;
+          const double X = KD[jk * S::KDW + 0] - Pb0, Y = KD[jk * S::KDW + 1] - Pb1,
+                       Zc = KD[jk * S::KDW + 2] - Pb2;
+          const double *Aj = AS + jk * (L + 1);
+          double *base = lds + S::oRp + jj * S::PJ;
+          const int tu = linetu[line];
+          const int T = tu & 255, U = tu >> 8;
+          double rl[LP + 1];
+          if (lap) {
+            double r1[LP + 1], r2[LP + 1], r3[LP + 1];
+            r_line<L, LP + 1, 0>(T + 2, U, X, Y, Zc, Aj, hc, r1);
+            r_line<L, LP + 1, 0>(T, U + 2, X, Y, Zc, Aj, hc, r2);
+            r_line<L, LP + 1, 2>(T, U, X, Y, Zc, Aj, hc, r3);
+#pragma unroll
+            for (int w = 0; w <= LP; ++w) rl[w] = r1[w] + r2[w] + r3[w];
+          } else if (dv) {
+            r_line<L, LP + 1, 1>(T, U, X, Y, Zc, Aj, hc, rl);
+          } else {
+            r_line<L, LP + 1, 0>(T + dt, U + du, X, Y, Zc, Aj, hc, rl);
+          }
+          const double *ez = base + S::jEk + 2 * NE;
+          double ezr[NE];
+#pragma unroll
+          for (int e = 0; e < NE; ++e) ezr[e] = ez[e];
+          double *zo = base + S::jZ + line * S::ZST;
+#pragma unroll
+          for (int v = 0; v <= LAB; ++v) {
 #pragma unroll
             for (int fz = 0; fz <= LCD; ++fz) {
               double acc = 0.0;
 #pragma unroll
-              for (int ph = 0; ph <= fz; ++ph) acc = fma(ez[fz * (fz + 1) / 2 + ph], r[ph], acc);
-              zo[fz] = acc;
+              for (int ph = 0; ph <= fz; ++ph)
+                if (v + ph <= LP) acc = fma(ezr[fz * (fz + 1) / 2 + ph], rl[v + ph], acc);
+              zo[v * (LCD + 1) + fz] = acc;
             }
           }
         }
         __syncthreads();
         // y pass
-        {
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+          double *base = lds + S::oRp + jj * S::PJ;
           double ey[NE];
 #pragma unroll
-          for (int k = 0; k < NE; ++k) ey[k] = Ek[NE + k];
+          for (int k = 0; k < NE; ++k) ey[k] = base[S::jEk + NE + k];
           for (int k = tid; k < S::NYT; k += NT) {
             const int fz = k % (LCD + 1);
             const int r1 = k / (LCD + 1);
@@ -337,8 +424,8 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
             if (T + v + fz > LP) continue;
             const int line0 = T * (LP + 1) - T * (T - 1) / 2;
             double col[LP + 1];
-            load_col<LP + 1, S::ZST>(Zb + line0 * S::ZST + v * (LCD + 1) + fz, LP - T, col);
-            double *yo = Yb + T * S::YST + v * NE + fz;
+            load_col<LP + 1, S::ZST>(base + S::jZ + line0 * S::ZST + v * (LCD + 1) + fz, LP - T, col);
+            double *yo = base + S::jY + T * S::YST + v * NE + fz;
 #pragma unroll
             for (int u = 0; u <= LAB; ++u) {
               if (u + v > LAB) continue;
@@ -356,10 +443,13 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
         }
         __syncthreads();
         // x pass into the register slots
-        {
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+          const double *base = lds + S::oRp + jj * S::PJ;
+          const double *Yb = base + S::jY;
           double ex[NE];
 #pragma unroll
-          for (int k = 0; k < NE; ++k) ex[k] = Ek[k];
+          for (int k = 0; k < NE; ++k) ex[k] = base[S::jEk + k];
 #pragma unroll
           for (int fx = 0; fx <= LCD; ++fx) {
 #pragma unroll
@@ -370,12 +460,13 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
                 double acc = 0.0;
 #pragma unroll
                 for (int ta = 0; ta <= fx; ++ta) acc = fma(ex[fx * (fx + 1) / 2 + ta], Yb[yb + ta * S::YST], acc);
-                wacc[slot] = fma(ckd, acc, wacc[slot]);
+                wacc[slot] = fma(ckdj[jj], acc, wacc[slot]);
               }
             }
           }
         }
-        __syncthreads();  // Ek, Y and R are rewritten for the next ket primitive
+        __syncthreads();  // Ek, Y and R are rewritten for the next ket primitives
+      }
       }
       // stage V[h][f] (dense f over |f| <= LCD) for the bra transform
       double *Vs = lds + S::oRp;
@@ -464,24 +555,35 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
   hrr_store(Uf, la, lb, lc, ld, nf, CD, a.out + o, tid, NT);
 }
 
+// Ket primitives per pass: more when the shape's LDS is small, so that
+// several work-groups still share a CU.
+template <int LAB, int LCD, int MODE>
+constexpr int pick_nj() {
+  if (BigShape<LAB, LCD, MODE, 4>::BYTES <= 40 * 1024) return 4;
+  if (BigShape<LAB, LCD, MODE, 2>::BYTES <= 64 * 1024) return 2;
+  return 1;
+}
+
 template <int LAB, int LCD, int MODE>
 inline int launch_big_t(const ContractArgs &a, unsigned nblocks, hipStream_t st) {
-  using S = BigShape<LAB, LCD, MODE>;
+  constexpr int NJ = pick_nj<LAB, LCD, MODE>();
+  using S = BigShape<LAB, LCD, MODE, NJ>;
+  static_assert(S::BYTES <= 160 * 1024, "LDS per work-group");
   static bool attr = false;
   if (!attr) {
-    if (hipFuncSetAttribute((const void *)big_kernel<LAB, LCD, MODE>,
+    if (hipFuncSetAttribute((const void *)big_kernel<LAB, LCD, MODE, NJ>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::BYTES) != hipSuccess)
       return -1;
     attr = true;
   }
-  hipLaunchKernelGGL((big_kernel<LAB, LCD, MODE>), dim3(nblocks), dim3(256), S::BYTES, st, a);
+  hipLaunchKernelGGL((big_kernel<LAB, LCD, MODE, NJ>), dim3(nblocks), dim3(256), S::BYTES, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // The Laplacian form of I5 is used where its LDS and register slots fit.
 template <int LAB, int LCD>
 constexpr bool lap_fits() {
-  using S = BigShape<LAB + 2, LCD, 2>;
+  using S = BigShape<LAB + 2, LCD, 2, 1>;
   return S::BYTES <= 160 * 1024 && S::MAXW <= 40 && S::MAXU <= 32;
 }
 

@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(128) aux_kernel(const KernelDev *__restrict__ 
 struct CLayout {
   int Lab, Lcd, Lp, L, HL, HLl, Hab, nf, nab, ncd, NE, Eab1, nlP, nuv, sw;
   int zsz, ysz, neb;
-  int blk, gR0, gR1, gRl, gZ, gY, gEk, gW, gEb, gU, gstride;
+  int blk, gR0, gR1, gRl, gZ, gY, gEk, gA, gW, gEb, gU, gstride;
   int grp, red, ufin, dbl, ints;
 };
 
@@ -445,6 +445,7 @@ __host__ __device__ inline void make_layout(int la, int lb, int lc, int ld, int 
   y.gZ = o; o += y.zsz;
   y.gY = o; o += y.ysz;
   y.gEk = o; o += 3 * y.NE;
+  y.gA = o; o += LTOT_MAX + 1;
   y.gW = o; o += y.Hab * y.nf;
   if (perprim) {
     y.gEb = o; o += y.neb;
@@ -475,7 +476,10 @@ __device__ __forceinline__ void gsync() {
 // R^(0)_{tuv}, t+u+v <= L, into the returned buffer (ridx layout).
 template <int GS>
 __device__ double *build_r(const int *tuv, int L, int lt, const double *A, int64_t np, int64_t pl,
-                           double X0, double X1, double X2, double *R0, double *R1) {
+                           double X0, double X1, double X2, double *R0, double *R1, double *As) {
+  // A_0..A_L staged in LDS first: one round of global loads, not one per level
+  for (int n = lt; n <= L; n += GS) As[n] = A[(int64_t)n * np + pl];
+  gsync<GS>();
   double *rc = R0, *rn = R1;
   for (int n = L; n >= 0; --n) {
     const int cnt = hsize(L - n);
@@ -484,7 +488,7 @@ __device__ double *build_r(const int *tuv, int L, int lt, const double *A, int64
       const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
       double val;
       if (idx == 0) {
-        val = A[(int64_t)n * np + pl];
+        val = As[n];
       } else if (t > 0) {
         val = X0 * rc[ridx(t - 1, u, v)];
         if (t > 1) val += (t - 1) * rc[ridx(t - 2, u, v)];
@@ -684,7 +688,7 @@ __global__ void __launch_bounds__(256) contract_kernel(ContractArgs a) {
       const double cab = bra.cab[ppb];
       const int64_t pl = qp0 + (int64_t)ib * nket + jk;
       gsync<GS>();
-      const double *R = build_r<GS>(tuv, L, lt, a.A, a.np, pl, X0, X1, X2, R0, R1);
+      const double *R = build_r<GS>(tuv, L, lt, a.A, a.np, pl, X0, X1, X2, R0, R1, gb + y.gA);
       if (i5) {
         for (int idx = lt; idx < y.HLl; idx += GS) {
           const int code = tuv[idx];
@@ -742,7 +746,7 @@ __global__ void __launch_bounds__(256) contract_kernel(ContractArgs a) {
           const double ckd = ket.cab[ppk] * exp(-(ket.ea[ppk] * ed / qk) * CD2);
           const int64_t pl = qp0 + (int64_t)ib * nket + jk;
           gsync<GS>();
-          const double *R = build_r<GS>(tuv, L, lt, a.A, a.np, pl, X0, X1, X2, R0, R1);
+          const double *R = build_r<GS>(tuv, L, lt, a.A, a.np, pl, X0, X1, X2, R0, R1, gb + y.gA);
           if (i5 && comp == 0) {
             for (int idx = lt; idx < y.HLl; idx += GS) {
               const int code = tuv[idx];
