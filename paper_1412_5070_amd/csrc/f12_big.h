@@ -1,5 +1,5 @@
 // E.R.E contraction specialised on the class shape (L_ab = l_a + l_b,
-// L_cd = l_c + l_d, I5 or not) for the classes with L_ab + L_cd (+2) > 4.
+// L_cd = l_c + l_d, I5 or not).
 //
 // One work-group of 256 threads per contracted quartet; all threads work on
 // one primitive quartet at a time.  Per primitive quartet (bra i, ket j):
@@ -587,22 +587,13 @@ constexpr bool lap_fits() {
   return S::BYTES <= 160 * 1024 && S::MAXW <= 40 && S::MAXU <= 32;
 }
 
-// Shapes handled here: L_ab + L_cd + (I5 ? 2 : 0) > 4.
-constexpr bool big_shape(int lab, int lcd, bool i5) { return lab + lcd + (i5 ? 2 : 0) > 4; }
-
 template <int LAB>
 inline int launch_big_lab(int lcd, int i5, const ContractArgs &a, unsigned nblocks, hipStream_t st) {
-#define F12_BIG_CASE(LCD)                                                              \
-  case LCD:                                                                            \
-    if (i5) {                                                                          \
-      if constexpr (big_shape(LAB, LCD, true)) {                                       \
-        if constexpr (lap_fits<LAB, LCD>()) return launch_big_t<LAB + 2, LCD, 2>(a, nblocks, st); \
-        else return launch_big_t<LAB, LCD, 1>(a, nblocks, st);                          \
-      }                                                                                \
-    } else {                                                                           \
-      if constexpr (big_shape(LAB, LCD, false)) return launch_big_t<LAB, LCD, 0>(a, nblocks, st); \
-    }                                                                                  \
-    return -1;
+#define F12_BIG_CASE(LCD)                                                                 \
+  case LCD:                                                                               \
+    if (!i5) return launch_big_t<LAB, LCD, 0>(a, nblocks, st);                            \
+    if constexpr (lap_fits<LAB, LCD>()) return launch_big_t<LAB + 2, LCD, 2>(a, nblocks, st); \
+    else return launch_big_t<LAB, LCD, 1>(a, nblocks, st);
   switch (lcd) {
     F12_BIG_CASE(0)
     F12_BIG_CASE(1)

@@ -95,18 +95,13 @@ __device__ inline void e_table(double a, double b, double AB, int la, int lb, do
 }
 #undef EI
 
-__device__ __forceinline__ void group_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 struct ContractArgs {
   PairsDev bra, ket;
   const int64_t *qb, *qk, *qoff, *qprim;
   int64_t qa, p0, np;
   const double *A;
-  int la, lb, lc, ld, i5, sw;
+  int la, lb, lc, ld, i5;
   double *out;
   int64_t out_base;
 };
@@ -127,18 +122,6 @@ __device__ __forceinline__ double ipow(double x, int n) {
   return r;
 }
 
-// Division of small non-negative ints by a per-launch constant d without the
-// integer-division sequence: q = (n * ceil(2^32/d)) >> 32 is exact while
-// n * d < 2^32 (task indices here stay below 2^20, divisors below 2^10).
-struct FastDiv {
-  uint64_t m;
-  int d;
-  __device__ __forceinline__ void init(int dd) {
-    d = dd;
-    m = ((1ull << 32) + (uint64_t)dd - 1) / (uint64_t)dd;
-  }
-  __device__ __forceinline__ int div(int n) const { return (int)(((uint64_t)n * m) >> 32); }
-};
 
 // Ket one-centre E^f_phi, f <= Lcd, at E[f(f+1)/2 + phi].
 __device__ inline void e_onecentre(double q, double XQC, int Lcd, double *E) {

@@ -384,410 +384,9 @@ __global__ void __launch_bounds__(128) aux_kernel(const KernelDev *__restrict__ 
 
 
 // ---------------------------------------------------------------------------
-// K5/K6: Hermite integrals and the E.R.E contraction (Eq. (ii)).
-//
-// The ket side uses one-centre expansions: x_C^f exp(-q x_Q^2) =
-// sum_phi E^f_phi Lambda_phi(x_Q) with E^{f+1}_phi = E^f_{phi-1}/(2q) +
-// X_QC E^f_phi + (phi+1) E^f_{phi+1}, so that per primitive quartet only
-//   V[h][f] = sum_{tau,nu,phi} E^fx_tau E^fy_nu E^fz_phi R_{h+(tau,nu,phi)}
-// for |f| in [l_c, l_c+l_d] is formed, as three one-dimensional passes
-// (z, then y, then x) through LDS.  V is summed over ket primitives, the bra
-// transform (two-centre E^{ab}, with the (-1)^{t+u+v} of Eq. (ii)) is applied
-// per bra primitive, and the exponent-free transfer
-//   x_D^d = sum_k C(d,k) (C_x - D_x)^(d-k) x_C^k
-// turns (ab|f) into (ab|cd) once per contracted quartet.
-// R^(n)_{t+1,u,v} = t R^(n+1)_{t-1,u,v} + X_x R^(n+1)_{tuv} (X = Q - P),
-// from R^(n)_000 = A_n, is built level by level in LDS.
-//
-// One work-group of 256 threads per contracted quartet, split into groups of
-// GS lanes.  PERPRIM: groups take primitive quartets and do both transforms
-// (small classes).  Otherwise groups take ket primitives, their V partials
-// are summed in LDS per bra primitive, and each thread keeps MAXU (ab, f)
-// accumulators in registers.
-// I5 (Eq. (I5byI3_), gradient coefficient -1, i.e.
-// 1/2 (lap_A - lap_B) = (a-b)/(2p) lap_Q - grad_Q . grad_AB) runs four
-// components: comp 0 with (a-b)/(2p) E^ab and R_lap = R_{t+2,u,v} +
-// R_{t,u+2,v} + R_{t,u,v+2}; comp d with -F^ab_d and R shifted by one along d.
+// K5/K6: the Hermite integrals and the E.R.E contraction run in the
+// shape-specialised kernels of f12_big.h (instantiated in f12_big_lab*.hip).
 // ---------------------------------------------------------------------------
-
-struct CLayout {
-  int Lab, Lcd, Lp, L, HL, HLl, Hab, nf, nab, ncd, NE, Eab1, nlP, nuv, sw;
-  int zsz, ysz, neb;
-  int blk, gR0, gR1, gRl, gZ, gY, gEk, gA, gW, gEb, gU, gstride;
-  int grp, red, ufin, dbl, ints;
-};
-
-__host__ __device__ inline void make_layout(int la, int lb, int lc, int ld, int i5, int sw,
-                                            bool perprim, int ng, CLayout &y) {
-  y.Lab = la + lb;
-  y.Lcd = lc + ld;
-  y.Lp = y.Lab + y.Lcd;
-  y.L = y.Lp + (i5 ? 2 : 0);
-  y.HL = hs3(y.L);
-  y.HLl = i5 ? hs3(y.L - 2) : 0;
-  y.Hab = hs3(y.Lab);
-  y.nf = hs3(y.Lcd) - hs3(lc - 1);
-  y.nab = nc2(la) * nc2(lb);
-  y.ncd = nc2(lc) * nc2(ld);
-  y.NE = nc2(y.Lcd);
-  y.Eab1 = (la + 1) * (lb + 1) * (y.Lab + 1);
-  y.nlP = nc2(y.Lp);
-  y.nuv = nc2(y.Lab);
-  y.sw = sw;
-  y.zsz = y.nlP * (y.Lab + 1) * sw;
-  y.ysz = (y.Lp + 1) * y.nuv * (y.Lcd + 1) * sw;
-  y.neb = (i5 ? 6 : 3) * y.Eab1;
-  y.blk = perprim ? 0 : y.neb;
-  int o = 0;
-  y.gR0 = o; o += y.HL;
-  y.gR1 = o; o += y.HL;
-  y.gRl = o; o += y.HLl;
-  y.gZ = o; o += y.zsz;
-  y.gY = o; o += y.ysz;
-  y.gEk = o; o += 3 * y.NE;
-  y.gA = o; o += LTOT_MAX + 1;
-  y.gW = o; o += y.Hab * y.nf;
-  if (perprim) {
-    y.gEb = o; o += y.neb;
-    y.gU = o; o += y.nab * y.nf;
-  } else {
-    y.gEb = -1;
-    y.gU = -1;
-  }
-  y.gstride = o;
-  const int nu = y.nab * y.nf;
-  y.grp = ng * y.gstride;
-  if (!perprim && y.grp < nu) y.grp = nu;  // (ab|f) staging aliases the group area
-  y.red = perprim ? (nu > 256 ? nu : 256) : 0;
-  y.ufin = perprim ? nu : 0;
-  y.dbl = y.blk + y.grp + y.red + y.ufin;
-  y.ints = y.HL + y.nlP + y.nuv;
-}
-
-
-template <int GS>
-__device__ __forceinline__ void gsync() {
-  if constexpr (GS > 64)
-    __syncthreads();
-  else
-    group_sync();
-}
-
-// R^(0)_{tuv}, t+u+v <= L, into the returned buffer (ridx layout).
-template <int GS>
-__device__ double *build_r(const int *tuv, int L, int lt, const double *A, int64_t np, int64_t pl,
-                           double X0, double X1, double X2, double *R0, double *R1, double *As) {
-  // A_0..A_L staged in LDS first: one round of global loads, not one per level
-  for (int n = lt; n <= L; n += GS) As[n] = A[(int64_t)n * np + pl];
-  gsync<GS>();
-  double *rc = R0, *rn = R1;
-  for (int n = L; n >= 0; --n) {
-    const int cnt = hsize(L - n);
-    for (int idx = lt; idx < cnt; idx += GS) {
-      const int code = tuv[idx];
-      const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
-      double val;
-      if (idx == 0) {
-        val = As[n];
-      } else if (t > 0) {
-        val = X0 * rc[ridx(t - 1, u, v)];
-        if (t > 1) val += (t - 1) * rc[ridx(t - 2, u, v)];
-      } else if (u > 0) {
-        val = X1 * rc[ridx(t, u - 1, v)];
-        if (u > 1) val += (u - 1) * rc[ridx(t, u - 2, v)];
-      } else {
-        val = X2 * rc[ridx(t, u, v - 1)];
-        if (v > 1) val += (v - 1) * rc[ridx(t, u, v - 2)];
-      }
-      rn[idx] = val;
-    }
-    gsync<GS>();
-    double *tmp = rc;
-    rc = rn;
-    rn = tmp;
-  }
-  return rc;
-}
-
-// Ket transform of one primitive quartet into W[ridx(t,u,v) * nf + f]
-// (accumulate: W += ckd * V, else W = ckd * V).  src holds R (or R_lap),
-// read at (T+dt, U+du, w+dv).
-template <int GS>
-__device__ void ket_passes(const CLayout &y, int lc, int lt, const int *linetu, const int *uvtab,
-                           const double *src, int dt, int du, int dv, const double *Ek,
-                           double ckd, double *Z, double *Y, double *W, bool accumulate) {
-  const int Lab = y.Lab, Lcd = y.Lcd, Lp = y.Lp, sw = y.sw, nuv = y.nuv, nf = y.nf;
-  const double *Ex = Ek, *Ey = Ek + y.NE, *Ez = Ek + 2 * y.NE;
-  FastDiv dv1, dvy, dvc, dvs, dvu;
-  dv1.init(Lab + 1);
-  dvy.init(nuv * (Lcd + 1));
-  dvc.init(Lcd + 1);
-  dvs.init(sw);
-  dvu.init(nuv);
-  for (int fz0 = 0; fz0 <= Lcd; fz0 += sw) {
-    // z: Z[line(T,U)][v][fz] = sum_phi Ez[fz][phi] R[T,U,v+phi]
-    const int nz = y.nlP * (Lab + 1);
-    for (int k = lt; k < nz; k += GS) {
-      const int line = dv1.div(k), v = k - line * (Lab + 1);
-      const int tu = linetu[line];
-      const int T = tu & 255, U = tu >> 8;
-      for (int fzl = 0; fzl < sw; ++fzl) {
-        const int fz = fz0 + fzl;
-        if (fz > Lcd || T + U + v + fz > Lp) break;
-        const double *e = Ez + fz * (fz + 1) / 2;
-        double s = 0.0;
-        for (int ph = 0; ph <= fz; ++ph) s += e[ph] * src[ridx(T + dt, U + du, v + ph + dv)];
-        Z[(line * (Lab + 1) + v) * sw + fzl] = s;
-      }
-    }
-    gsync<GS>();
-    // y: Y[T][uv][fy][fz] = sum_nu Ey[fy][nu] Z[line(T,u+nu)][v][fz]
-    const int ny = (Lp + 1) * nuv * (Lcd + 1);
-    for (int k = lt; k < ny; k += GS) {
-      const int T = dvy.div(k);
-      const int r = k - T * (nuv * (Lcd + 1));
-      const int uvi = dvc.div(r), fy = r - uvi * (Lcd + 1);
-      const int uv = uvtab[uvi];
-      const int u = uv & 255, v = uv >> 8;
-      const double *e = Ey + fy * (fy + 1) / 2;
-      for (int fzl = 0; fzl < sw; ++fzl) {
-        const int fz = fz0 + fzl;
-        if (fz + fy > Lcd || T + u + v + fy + fz > Lp) break;
-        double s = 0.0;
-        for (int nu = 0; nu <= fy; ++nu) {
-          const int line = T * (Lp + 1) - T * (T - 1) / 2 + u + nu;
-          s += e[nu] * Z[(line * (Lab + 1) + v) * sw + fzl];
-        }
-        Y[((T * nuv + uvi) * (Lcd + 1) + fy) * sw + fzl] = s;
-      }
-    }
-    gsync<GS>();
-    // x: W[t,u,v][f] (+)= ckd sum_tau Ex[fx][tau] Y[t+tau][uv][fy][fz]
-    const int nx = (Lab + 1) * nuv * (Lcd + 1) * sw;
-    for (int k = lt; k < nx; k += GS) {
-      int r = dvs.div(k);
-      const int fzl = k - r * sw;
-      const int r2 = dvc.div(r);
-      const int fy = r - r2 * (Lcd + 1);
-      const int t = dvu.div(r2);
-      const int uvi = r2 - t * nuv;
-      const int uv = uvtab[uvi];
-      const int u = uv & 255, v = uv >> 8;
-      const int fz = fz0 + fzl;
-      if (t + u + v > Lab || fz > Lcd || fy + fz > Lcd) continue;
-      const int fxlo = lc - fy - fz > 0 ? lc - fy - fz : 0;
-      const int fxhi = Lcd - fy - fz;
-      const int h = ridx(t, u, v);
-      for (int fx = fxlo; fx <= fxhi; ++fx) {
-        const double *e = Ex + fx * (fx + 1) / 2;
-        double s = 0.0;
-        for (int ta = 0; ta <= fx; ++ta)
-          s += e[ta] * Y[(((t + ta) * nuv + uvi) * (Lcd + 1) + fy) * sw + fzl];
-        const int wi = h * nf + findex(fx, fy, fz, lc);
-        W[wi] = accumulate ? fma(ckd, s, W[wi]) : ckd * s;
-      }
-    }
-    gsync<GS>();
-  }
-}
-
-// Bra transform of one (ab, f) element: sum_h (-1)^{|h|} E^ab_h W[h][f].
-__device__ __forceinline__ double bra_elem(int e, int nf, int la, int lb, int Lab, int Eab1,
-                                           const double *Eb, const double *Fb, int comp,
-                                           const double *W) {
-  const int nb = ncart(lb);
-  const int ab = e / nf, f = e - ab * nf;
-  int ax, ay, az, bx, by, bz;
-  cart_comp(la, ab / nb, ax, ay, az);
-  cart_comp(lb, ab % nb, bx, by, bz);
-  const double *ex = (comp == 1 ? Fb : Eb) + (ax * (lb + 1) + bx) * (Lab + 1);
-  const double *ey = (comp == 2 ? Fb : Eb) + Eab1 + (ay * (lb + 1) + by) * (Lab + 1);
-  const double *ez = (comp == 3 ? Fb : Eb) + 2 * Eab1 + (az * (lb + 1) + bz) * (Lab + 1);
-  double s = 0.0;
-  for (int t = 0; t <= ax + bx; ++t)
-    for (int u = 0; u <= ay + by; ++u) {
-      const double exy = ((t + u) & 1) ? -ex[t] * ey[u] : ex[t] * ey[u];
-      double sv = 0.0;
-      for (int v = 0; v <= az + bz; ++v) {
-        const double term = ez[v] * W[ridx(t, u, v) * nf + f];
-        sv += (v & 1) ? -term : term;
-      }
-      s = fma(exy, sv, s);
-    }
-  return s;
-}
-
-template <int GS, int MAXU, bool PERPRIM>
-__global__ void __launch_bounds__(256) contract_kernel(ContractArgs a) {
-  constexpr int NT = 256;
-  constexpr int NG = NT / GS;
-  extern __shared__ double lds[];
-  const int tid = threadIdx.x;
-  const int g = tid / GS, lt = tid % GS;
-  const int la = a.la, lb = a.lb, lc = a.lc, ld = a.ld, i5 = a.i5;
-  CLayout y;
-  make_layout(la, lb, lc, ld, i5, a.sw, PERPRIM, NG, y);
-  const int Lab = y.Lab, Lcd = y.Lcd, Lp = y.Lp, L = y.L, nf = y.nf;
-  const int nu = y.nab * nf;
-  double *grp = lds + y.blk;
-  double *gb = grp + (size_t)g * y.gstride;
-  int *tuv = (int *)(lds + y.dbl);
-  int *linetu = tuv + y.HL;
-  int *uvtab = linetu + y.nlP;
-  for (int idx = tid; idx < y.HL; idx += NT) {
-    int N = 0;
-    while (hsize(N) <= idx) ++N;
-    const int r = idx - (N > 0 ? hsize(N - 1) : 0);
-    int s = 0;
-    while ((s + 1) * (s + 2) / 2 <= r) ++s;
-    const int u = s - (r - s * (s + 1) / 2);
-    const int t = N - s;
-    tuv[idx] = t | (u << 8) | ((N - t - u) << 16);
-  }
-  if (tid == 0) {
-    int k = 0;
-    for (int T = 0; T <= Lp; ++T)
-      for (int U = 0; U <= Lp - T; ++U) linetu[k++] = T | (U << 8);
-    k = 0;
-    for (int u = 0; u <= Lab; ++u)
-      for (int v = 0; v <= Lab - u; ++v) uvtab[k++] = u | (v << 8);
-  }
-  __syncthreads();
-
-  const int64_t q = a.qa + blockIdx.x;
-  const int64_t bp = a.qb[q], kp = a.qk[q];
-  const PairsDev &bra = a.bra, &ket = a.ket;
-  const int nbra = bra.ka[bp] * bra.kb[bp];
-  const int nket = ket.ka[kp] * ket.kb[kp];
-  const double ABb[3] = {bra.ABx[bp], bra.ABy[bp], bra.ABz[bp]};
-  const double CD[3] = {ket.ABx[kp], ket.ABy[kp], ket.ABz[kp]};
-  const double CD2 = CD[0] * CD[0] + CD[1] * CD[1] + CD[2] * CD[2];
-  const int64_t qp0 = a.qprim[q] - a.p0;
-  const int64_t o = a.qoff[q] - a.out_base;
-  const int ncomp = i5 ? 4 : 1;
-  double *R0 = gb + y.gR0, *R1 = gb + y.gR1, *Rl = gb + y.gRl;
-  double *Zb = gb + y.gZ, *Yb = gb + y.gY, *Ek = gb + y.gEk, *Wg = gb + y.gW;
-  double *Ufin;
-
-  if constexpr (PERPRIM) {
-    double *Eb = gb + y.gEb, *Fb = Eb + 3 * y.Eab1, *Ug = gb + y.gU;
-    for (int e = lt; e < nu; e += GS) Ug[e] = 0.0;
-    const int nprim = nbra * nket;
-    for (int p = g; p < nprim; p += NG) {
-      const int ib = p / nket, jk = p - ib * nket;
-      const int64_t ppb = bra.pp_off[bp] + ib, ppk = ket.pp_off[kp] + jk;
-      const double ea = bra.ea[ppb], eb = bra.eb[ppb], pb = bra.p[ppb];
-      const double qk = ket.p[ppk], ed = ket.eb[ppk];
-      for (int d = lt; d < 3; d += GS) {
-        e_table(ea, eb, ABb[d], la, lb, Eb + d * y.Eab1, i5 ? Fb + d * y.Eab1 : nullptr);
-        e_onecentre(qk, -(ed / qk) * CD[d], Lcd, Ek + d * y.NE);
-      }
-      const double X0 = ket.Px[ppk] - bra.Px[ppb], X1 = ket.Py[ppk] - bra.Py[ppb],
-                   X2 = ket.Pz[ppk] - bra.Pz[ppb];
-      const double ckd = ket.cab[ppk] * exp(-(ket.ea[ppk] * ed / qk) * CD2);
-      const double cab = bra.cab[ppb];
-      const int64_t pl = qp0 + (int64_t)ib * nket + jk;
-      gsync<GS>();
-      const double *R = build_r<GS>(tuv, L, lt, a.A, a.np, pl, X0, X1, X2, R0, R1, gb + y.gA);
-      if (i5) {
-        for (int idx = lt; idx < y.HLl; idx += GS) {
-          const int code = tuv[idx];
-          const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
-          Rl[idx] = R[ridx(t + 2, u, v)] + R[ridx(t, u + 2, v)] + R[ridx(t, u, v + 2)];
-        }
-        gsync<GS>();
-      }
-      for (int comp = 0; comp < ncomp; ++comp) {
-        const double *src = (i5 && comp == 0) ? Rl : R;
-        ket_passes<GS>(y, lc, lt, linetu, uvtab, src, comp == 1, comp == 2, comp == 3, Ek, ckd,
-                       Zb, Yb, Wg, false);
-        const double cw = cab * (i5 ? (comp == 0 ? (ea - eb) / (2.0 * pb) : -1.0) : 1.0);
-        for (int e = lt; e < nu; e += GS)
-          Ug[e] = fma(cw, bra_elem(e, nf, la, lb, Lab, y.Eab1, Eb, Fb, comp, Wg), Ug[e]);
-        gsync<GS>();
-      }
-    }
-    __syncthreads();
-    // sum the group copies: rows of partial sums, then the rows
-    double *red = grp + y.grp;
-    Ufin = red + y.red;
-    const int RR = nu >= NT ? 1 : NT / nu;
-    for (int w = tid; w < RR * nu; w += NT) {
-      const int r = w / nu, e = w - r * nu;
-      double s = 0.0;
-      for (int gg = r; gg < NG; gg += RR) s += grp[(size_t)gg * y.gstride + y.gU + e];
-      red[w] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < nu; e += NT) {
-      double s = 0.0;
-      for (int r = 0; r < RR; ++r) s += red[r * nu + e];
-      Ufin[e] = s;
-    }
-    __syncthreads();
-  } else {
-    double *Eb = lds, *Fb = lds + 3 * y.Eab1;
-    double Uacc[MAXU];
-#pragma unroll
-    for (int k = 0; k < MAXU; ++k) Uacc[k] = 0.0;
-    for (int ib = 0; ib < nbra; ++ib) {
-      const int64_t ppb = bra.pp_off[bp] + ib;
-      const double ea = bra.ea[ppb], eb = bra.eb[ppb], pb = bra.p[ppb];
-      const double Pb0 = bra.Px[ppb], Pb1 = bra.Py[ppb], Pb2 = bra.Pz[ppb];
-      const double cab = bra.cab[ppb];
-      if (tid < 3) e_table(ea, eb, ABb[tid], la, lb, Eb + tid * y.Eab1, i5 ? Fb + tid * y.Eab1 : nullptr);
-      for (int comp = 0; comp < ncomp; ++comp) {
-        for (int e = lt; e < y.Hab * nf; e += GS) Wg[e] = 0.0;
-        for (int jk = g; jk < nket; jk += NG) {
-          const int64_t ppk = ket.pp_off[kp] + jk;
-          const double qk = ket.p[ppk], ed = ket.eb[ppk];
-          for (int d = lt; d < 3; d += GS) e_onecentre(qk, -(ed / qk) * CD[d], Lcd, Ek + d * y.NE);
-          const double X0 = ket.Px[ppk] - Pb0, X1 = ket.Py[ppk] - Pb1, X2 = ket.Pz[ppk] - Pb2;
-          const double ckd = ket.cab[ppk] * exp(-(ket.ea[ppk] * ed / qk) * CD2);
-          const int64_t pl = qp0 + (int64_t)ib * nket + jk;
-          gsync<GS>();
-          const double *R = build_r<GS>(tuv, L, lt, a.A, a.np, pl, X0, X1, X2, R0, R1, gb + y.gA);
-          if (i5 && comp == 0) {
-            for (int idx = lt; idx < y.HLl; idx += GS) {
-              const int code = tuv[idx];
-              const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
-              Rl[idx] = R[ridx(t + 2, u, v)] + R[ridx(t, u + 2, v)] + R[ridx(t, u, v + 2)];
-            }
-            gsync<GS>();
-          }
-          const double *src = (i5 && comp == 0) ? Rl : R;
-          ket_passes<GS>(y, lc, lt, linetu, uvtab, src, comp == 1, comp == 2, comp == 3, Ek, ckd,
-                         Zb, Yb, Wg, true);
-        }
-        __syncthreads();
-        if (NG > 1) {
-          for (int e = tid; e < y.Hab * nf; e += NT) {
-            double s = 0.0;
-            for (int gg = 0; gg < NG; ++gg) s += grp[(size_t)gg * y.gstride + y.gW + e];
-            grp[y.gW + e] = s;
-          }
-          __syncthreads();
-        }
-        const double *W0 = grp + y.gW;
-        const double cw = cab * (i5 ? (comp == 0 ? (ea - eb) / (2.0 * pb) : -1.0) : 1.0);
-#pragma unroll
-        for (int k = 0; k < MAXU; ++k) {
-          const int e = tid + k * NT;
-          if (e < nu) Uacc[k] = fma(cw, bra_elem(e, nf, la, lb, Lab, y.Eab1, Eb, Fb, comp, W0), Uacc[k]);
-        }
-        __syncthreads();
-      }
-    }
-    Ufin = grp;
-#pragma unroll
-    for (int k = 0; k < MAXU; ++k) {
-      const int e = tid + k * NT;
-      if (e < nu) Ufin[e] = Uacc[k];
-    }
-    __syncthreads();
-  }
-  hrr_store(Ufin, la, lb, lc, ld, nf, CD, a.out + o, tid, NT);
-}
 
 // ---------------------------------------------------------------------------
 // Host-side launchers.
@@ -817,71 +416,6 @@ int launch_aux(const KernelDev *K, const PairsDev &bra, const PairsDev &ket, con
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Launch plan per class: mode, lanes per group, fz values per slice, bra
-// accumulators per thread; LDS bytes from the same layout the kernel uses.
-struct ContractPlan {
-  bool perprim;
-  int gs, maxu, sw;
-  size_t lds;
-};
-
-static size_t layout_bytes(const CLayout &y) { return (size_t)y.dbl * 8 + (size_t)y.ints * 4; }
-
-static bool contract_plan(int la, int lb, int lc, int ld, int i5, ContractPlan &P) {
-  const int Lab = la + lb, Lcd = lc + ld, L = Lab + Lcd + (i5 ? 2 : 0);
-  CLayout y;
-  if (L <= 4) {
-    P.perprim = true;
-    P.maxu = 1;
-    P.sw = Lcd + 1;
-    make_layout(la, lb, lc, ld, i5, P.sw, true, 1, y);
-    int maxt = hs3(L);
-    const int cand[4] = {y.nlP * (Lab + 1), (y.Lp + 1) * y.nuv * (Lcd + 1),
-                         (Lab + 1) * y.nuv * (Lcd + 1) * P.sw, y.nab * y.nf};
-    for (int c : cand) maxt = c > maxt ? c : maxt;
-    int gs = 1;
-    while (gs < 64 && 2 * gs < maxt) gs *= 2;
-    for (;;) {
-      make_layout(la, lb, lc, ld, i5, P.sw, true, 256 / gs, y);
-      if (layout_bytes(y) <= 64 * 1024 || gs == 64) break;
-      gs *= 2;
-    }
-    P.gs = gs;
-    P.lds = layout_bytes(y);
-    return P.lds <= 160 * 1024;
-  }
-  P.perprim = false;
-  make_layout(la, lb, lc, ld, i5, 1, false, 1, y);
-  const int nu = y.nab * y.nf;
-  P.maxu = nu <= 1024 ? 4 : nu <= 2048 ? 8 : nu <= 4096 ? 16 : 32;
-  if (nu > 256 * 32) return false;
-  const int gss[2] = {64, 256};
-  for (int gs : gss) {
-    const size_t cap = gs == 64 ? 80 * 1024 : 160 * 1024;
-    for (int sw = Lcd + 1; sw >= 1; --sw) {
-      make_layout(la, lb, lc, ld, i5, sw, false, 256 / gs, y);
-      if (layout_bytes(y) <= cap) {
-        P.gs = gs;
-        P.sw = sw;
-        P.lds = layout_bytes(y);
-        return true;
-      }
-    }
-  }
-  return false;
-}
-
-template <int GS, int MAXU, bool PERPRIM>
-static void launch_contract_t(const ContractArgs &a, unsigned nblocks, size_t lds, hipStream_t st) {
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void *)contract_kernel<GS, MAXU, PERPRIM>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr = true;
-  }
-  hipLaunchKernelGGL((contract_kernel<GS, MAXU, PERPRIM>), dim3(nblocks), dim3(256), lds, st, a);
-}
-
 int launch_big_lab0(int, int, const ContractArgs &, unsigned, hipStream_t);
 int launch_big_lab1(int, int, const ContractArgs &, unsigned, hipStream_t);
 int launch_big_lab2(int, int, const ContractArgs &, unsigned, hipStream_t);
@@ -908,9 +442,6 @@ int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
                     int64_t np, const double *A, int la, int lb, int lc, int ld, int i5,
                     double *out, int64_t out_base, hipStream_t stream) {
   if (nqc <= 0) return 0;
-  const bool big = la + lb + lc + ld + (i5 ? 2 : 0) > 4;
-  ContractPlan P;
-  if (!big && !contract_plan(la, lb, lc, ld, i5, P)) return -1;
   ContractArgs a;
   a.bra = bra;
   a.ket = ket;
@@ -927,36 +458,9 @@ int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
   a.lc = lc;
   a.ld = ld;
   a.i5 = i5;
-  a.sw = big ? 1 : P.sw;
   a.out = out;
   a.out_base = out_base;
-  const unsigned nb = (unsigned)nqc;
-  if (big) return launch_big(la + lb, lc + ld, i5, a, nb, stream);
-  if (P.perprim) {
-    switch (P.gs) {
-      case 1: launch_contract_t<1, 1, true>(a, nb, P.lds, stream); break;
-      case 2: launch_contract_t<2, 1, true>(a, nb, P.lds, stream); break;
-      case 4: launch_contract_t<4, 1, true>(a, nb, P.lds, stream); break;
-      case 8: launch_contract_t<8, 1, true>(a, nb, P.lds, stream); break;
-      case 16: launch_contract_t<16, 1, true>(a, nb, P.lds, stream); break;
-      case 32: launch_contract_t<32, 1, true>(a, nb, P.lds, stream); break;
-      case 64: launch_contract_t<64, 1, true>(a, nb, P.lds, stream); break;
-      default: return -1;
-    }
-  } else {
-    switch (P.gs * 100 + P.maxu) {
-      case 6404: launch_contract_t<64, 4, false>(a, nb, P.lds, stream); break;
-      case 6408: launch_contract_t<64, 8, false>(a, nb, P.lds, stream); break;
-      case 6416: launch_contract_t<64, 16, false>(a, nb, P.lds, stream); break;
-      case 6432: launch_contract_t<64, 32, false>(a, nb, P.lds, stream); break;
-      case 25604: launch_contract_t<256, 4, false>(a, nb, P.lds, stream); break;
-      case 25608: launch_contract_t<256, 8, false>(a, nb, P.lds, stream); break;
-      case 25616: launch_contract_t<256, 16, false>(a, nb, P.lds, stream); break;
-      case 25632: launch_contract_t<256, 32, false>(a, nb, P.lds, stream); break;
-      default: return -1;
-    }
-  }
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  return launch_big(la + lb, lc + ld, i5, a, (unsigned)nqc, stream);
 }
 
 // Diagnostic: A_n for explicit (p, q, R) triples (one thread each), R along z.
