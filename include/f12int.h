@@ -173,8 +173,8 @@ int f12_quartets_scratch_prims(const f12_quartets *q, int64_t *n_prim_quartets);
  * for n primitive quartets given by exponent sums p, q and distance R.
  * d_p, d_q, d_R: device double[n]; d_A: device double[(L+1) n] with A_k of
  * point i at d_A[k*n + i].  route: 0 = the switch f12_eval uses (small-T
- * series below T = xi R^2 = 2.5 / 4.5 / 6 for L <= 4 / <= 8 / > 8, the
- * large-T lowering route above);
+ * series below T = xi R^2 = 1 for L <= 3, 1.5, 2, 2, 2.5, 3, 3.5, 4, 4.5, 5
+ * for L = 4..12 and 6 for L = 13, 14; the large-T lowering route above);
  * 1 = small-T series; 2 = large-T route with the exp(-xi (r+R)^2) side kept.
  * Asynchronous on `stream`. */
 int f12_aux_radial(const f12_kernel *k, int64_t n, const double *d_p, const double *d_q,

@@ -323,10 +323,15 @@ __device__ void aux_small(const KernelDev *__restrict__ K, double xi, double u, 
 }
 
 // Small-T / large-T switch and the cut for the exp(-xi (r+R)^2) side.
-// Both routes reach ~1e-15 of the (2 xi)^n-scaled envelope of A_n in an
-// overlap: the DD series for T <= 14, the lowering route for T >= 4 (T >= 2
-// when L <= 4).  The switch sits inside it.
-__device__ __forceinline__ double t_switch(int L) { return L <= 4 ? 2.5 : (L <= 8 ? 4.5 : 6.0); }
+// The lowering route holds ~1e-14 of the (2 xi)^n-scaled envelope of A_n from
+// T = 1 (L <= 3), 1.5 (L = 4), 2 (L = 5, 6), 2.5, 3, 3.5, 4, 4.5, 5 (L = 7..12)
+// and 6 (L = 13, 14), measured against the DD series, which holds to
+// T = 14; below those T the DD series runs.
+__device__ __forceinline__ double t_switch(int L) {
+  constexpr double sw[LTOT_MAX + 1] = {1.0, 1.0, 1.0, 1.0, 1.5, 2.0, 2.0, 2.5,
+                                       3.0, 3.5, 4.0, 4.5, 5.0, 6.0, 6.0};
+  return sw[L < 0 ? 0 : (L > LTOT_MAX ? LTOT_MAX : L)];
+}
 __device__ __forceinline__ bool minus_side_needed(double T, int L) {
   // keep the F(-R) branch while exp(-T) (2T)^L / (2L-1)!! > 1e-19
   double lg = -T;

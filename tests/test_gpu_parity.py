@@ -66,13 +66,14 @@ def test_radial_derivatives_vs_oracle(lib, cls, fac, facp, L):
 
 def test_radial_routes_agree_in_overlap(lib):
     """Branch consistency: the DD small-T series and the large-T lowering
-    route agree where both are valid (4 <= T <= 12)."""
+    route agree from the switch point of each L (1.5 for L = 4, 3 for L = 8,
+    5 for L = 12) up to T = 12."""
     rng = np.random.default_rng(11)
     for cls, fac in ((3, P1), (6, P1), (2, FACTOR_SETS["P4"])):
         k = lib.Kernel(cls, fac, fac)
-        for L in (4, 8, 12):
+        for L, Tsw in ((4, 1.5), (8, 3.0), (12, 5.0)):
             pts = []
-            for T in (4.0, 6.0, 9.0, 12.0):
+            for T in (Tsw, Tsw + 1.0, 9.0, 12.0):
                 for _ in range(4):
                     p, q = 10 ** rng.uniform(-1, 2), 10 ** rng.uniform(-1, 2)
                     pts.append((p, q, math.sqrt(T * (p + q) / (p * q))))
