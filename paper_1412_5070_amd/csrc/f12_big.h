@@ -468,8 +468,12 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
         __syncthreads();  // Ek, Y and R are rewritten for the next ket primitives
       }
       }
-      // stage V[h][f] (dense f over |f| <= LCD) for the bra transform
+      // stage V[t,u,v][f] (dense f over |f| <= LCD) for the bra transform,
+      // lines (t,u) in order, v contiguous: row vline(t,u) + v
       double *Vs = lds + S::oRp;
+      auto vline = [](int t, int u) {
+        return hs3(LAB) - hs3(LAB - t) + u * (LAB - t + 1) - u * (u - 1) / 2;
+      };
 #pragma unroll
       for (int fx = 0; fx <= LCD; ++fx) {
         const int M = LCD - fx;
@@ -487,7 +491,9 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
             }
             const int fz = rr;
             const int n = fx + fy + fz, s2 = fy + fz;
-            Vs[h * S::NF0 + hs3(n - 1) + s2 * (s2 + 1) / 2 + fz] = wacc[slot];
+            const int code = tuv[h];
+            const int t = code & 255, u = (code >> 8) & 255, v = code >> 16;
+            Vs[(vline(t, u) + v) * S::NF0 + hs3(n - 1) + s2 * (s2 + 1) / 2 + fz] = wacc[slot];
           }
         }
       }
@@ -516,9 +522,10 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
               for (int t = 0; t <= nx; ++t)
                 for (int u = 0; u <= ny; ++u) {
                   const double exy = ((t + u) & 1) ? -exr[t] * eyr[u] : exr[t] * eyr[u];
+                  const double *vr = Vs + vline(t, u) * S::NF0 + f;
                   double sv = 0.0;
                   for (int v = 0; v <= nz; ++v) {
-                    const double term = ezr[v] * Vs[ridx(t, u, v) * S::NF0 + f];
+                    const double term = ezr[v] * vr[v * S::NF0];
                     sv += (v & 1) ? -term : term;
                   }
                   sacc = fma(exy, sv, sacc);
@@ -531,9 +538,10 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
             for (int t = 0; t <= ax + bx; ++t)
               for (int u = 0; u <= ay + by; ++u) {
                 const double exy = ((t + u) & 1) ? -exr[t] * eyr[u] : exr[t] * eyr[u];
+                const double *vr = Vs + vline(t, u) * S::NF0 + f;
                 double sv = 0.0;
                 for (int v = 0; v <= az + bz; ++v) {
-                  const double term = ezr[v] * Vs[ridx(t, u, v) * S::NF0 + f];
+                  const double term = ezr[v] * vr[v * S::NF0];
                   sv += (v & 1) ? -term : term;
                 }
                 sacc = fma(exy, sv, sacc);

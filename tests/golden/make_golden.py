@@ -42,7 +42,7 @@ DF3_QUADS_I5 = [(3, 2, 6, 5), (2, 3, 6, 5), (7, 11, 1, 0), (0, 0, 11, 7), (6, 2,
                 (2, 2, 9, 4), (3, 2, 7, 11)]
 
 
-def plain20_quads(n_per_L=3, max_prim=64, seed=99):
+def plain20_quads(n_per_L=2, max_prim=64, seed=99):
     _, shells = config_plain()
     ls = np.array([s.l for s in shells])
     ks = np.array([len(s.exps) for s in shells])
@@ -82,9 +82,7 @@ def build(setname):
         jobs += [(setname, 3, q) for q in DF3_QUADS_I5 if q not in DF3_QUADS]
     else:
         quads = plain20_quads()
-        jobs = [(setname, c, q) for c in (2, 3, 4, 6) for q in quads]
-        q5 = [q for q in quads if sum(1 for _ in q) == 4][: len(quads)]
-        jobs += [(setname, 5, q) for q in q5]
+        jobs = [(setname, c, q) for c in (5, 2, 3, 4, 6) for q in quads]
     out = {}
     with Pool(int(os.environ.get("GOLDEN_PROCS", "6"))) as pool:
         for (sname, cls, quad), val in pool.imap_unordered(_job, jobs):
