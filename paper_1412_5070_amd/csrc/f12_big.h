@@ -370,7 +370,8 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
         // thread: Z[T,U][v][fz] = sum_phi E^fz_phi R_{T',U',v+phi+sh}, with
         // (T', U', sh) = (T, U, 0), the shifted line of an I5 component, or
         // the three terms of R_lap.
-        for (int k = tid; k < NJ * S::NLP; k += NT) {
+        const int nvj = nkc - jk0 < NJ ? nkc - jk0 : NJ;  // ket primitives in this pass
+        for (int k = tid; k < nvj * S::NLP; k += NT) {
           const int jj = k / S::NLP, line = k - jj * S::NLP;
           const int jk = jk0 + jj < nkc ? jk0 + jj : jk0;
           const double X = KD[jk * S::KDW + 0] - Pb0, Y = KD[jk * S::KDW + 1] - Pb1,
@@ -413,6 +414,7 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
         // y pass
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
+          if (jj >= nvj) break;
           double *base = lds + S::oRp + jj * S::PJ;
           double ey[NE];
 #pragma unroll
@@ -445,6 +447,7 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
         // x pass into the register slots
 #pragma unroll
         for (int jj = 0; jj < NJ; ++jj) {
+          if (jj >= nvj) break;
           const double *base = lds + S::oRp + jj * S::PJ;
           const double *Yb = base + S::jY;
           double ex[NE];
@@ -567,6 +570,7 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
 // several work-groups still share a CU.
 template <int LAB, int LCD, int MODE>
 constexpr int pick_nj() {
+  if (BigShape<LAB, LCD, MODE, 8>::BYTES <= 40 * 1024) return 8;
   if (BigShape<LAB, LCD, MODE, 4>::BYTES <= 40 * 1024) return 4;
   if (BigShape<LAB, LCD, MODE, 2>::BYTES <= 64 * 1024) return 2;
   return 1;

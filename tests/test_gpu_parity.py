@@ -168,3 +168,46 @@ def test_df_blocks_vs_golden(lib, cls):
     from make_golden import DF3_QUADS, DF3_QUADS_I5, df3_shells
     quads = DF3_QUADS_I5 if cls == 5 else DF3_QUADS
     _check_golden_set(lib, df3_shells(), _golden("df3"), cls, quads)
+
+
+@pytest.mark.parametrize("cls", [2, 3, 4, 6, 5])
+def test_plain20_sampled_vs_golden(lib, cls):
+    """The 20-atom workload at full size: the class's whole unique-quartet
+    list is built as bench.py builds it, and the stored oracle values of
+    quartets sampled from it (two per total angular momentum, at most 64
+    primitive quartets each) are compared with f12_eval on those entries."""
+    import os
+    import torch
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import plain20_quads
+    from synth import config_plain
+    golden = _golden("plain20")
+    _, shells = config_plain()
+    basis = lib.Basis.from_shells(shells)
+    pairs = lib.Pairs(basis, 0)
+    k = lib.Kernel(cls, P1, P1)
+    Q = lib.Quartets.build(pairs, pairs, cls)
+    quads = Q.quads().astype(np.int64)
+    offs = Q.offsets()
+    keys = ((quads[:, 0] * 128 + quads[:, 1]) * 128 + quads[:, 2]) * 128 + quads[:, 3]
+    sample = plain20_quads()
+    print(f"plain20 cls={cls} list={len(keys)} samples={len(sample)}", flush=True)
+    worst = 0.0
+    for qd in sample:
+        key = ((qd[0] * 128 + qd[1]) * 128 + qd[2]) * 128 + qd[3]
+        idx = np.nonzero(keys == key)[0]
+        assert len(idx) == 1, qd
+        i = int(idx[0])
+        out = torch.empty(int(offs[i + 1] - offs[i]), dtype=torch.float64, device="cuda")
+        lib.eval_into(Q, k, out, i, i + 1)
+        lib.stream_status()
+        got = out.cpu().numpy()
+        ref = golden["c%d_%d_%d_%d_%d" % ((cls,) + tuple(qd))]
+        if cls == 5:
+            ref3 = golden["c3_%d_%d_%d_%d" % tuple(qd)]
+            e = i5_block_err(got, ref, ref3, np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps]))
+        else:
+            e = block_rel_err(got, ref)
+        worst = max(worst, e)
+        print(f"  {qd} l={[shells[j].l for j in qd]} err {e:.2e}", flush=True)
+        assert e < 1e-12, (qd, e)
