@@ -66,20 +66,6 @@ __device__ double w_asym(double a, double X) {
   return F12_SQRTPI * pow(X, a) * sum;
 }
 
-__device__ __forceinline__ double w_eval(const FamilyDesc &F, int m, double X) {
-  if (X >= WX_HI) return w_asym(F.alpha0 + m, X);
-  double xs = (X - WX_LO) * WX_INVH;
-  int ix = (int)rint(xs);
-  ix = ix < 0 ? 0 : (ix >= F.nx ? F.nx - 1 : ix);
-  double Xg = WX_LO + ix * (1.0 / WX_INVH);
-  double d = X - Xg;
-  const double *row = F.table + (int64_t)ix * F.nm + (m - F.m_lo);
-  double td = 2.0 * d;
-  double s = row[KT];
-#pragma unroll
-  for (int k = KT; k >= 1; --k) s = fma(s, td * (1.0 / k), row[k - 1]);
-  return exp(-d * (2.0 * Xg + d)) * s;
-}
 
 // ---------------------------------------------------------------------------
 // Radial derivatives A_n = D^n B_i / N', D = R^-1 d/dR, n = 0..L.
@@ -135,9 +121,29 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
         } else {
           for (int i = 0; i < -mlo; ++i) gp *= sqg;
         }
-        for (int m = mlo; m <= mhi; ++m) {
-          Om[m - mlo] = gp * w_eval(F, m, X);
-          gp *= isq;
+        if (X >= WX_HI) {
+          for (int m = mlo; m <= mhi; ++m) {
+            Om[m - mlo] = gp * w_asym(F.alpha0 + m, X);
+            gp *= isq;
+          }
+        } else {
+          // one grid point and one exp factor for every order m
+          const double xs = (X - WX_LO) * WX_INVH;
+          int ix = (int)rint(xs);
+          ix = ix < 0 ? 0 : (ix >= F.nx ? F.nx - 1 : ix);
+          const double Xg = WX_LO + ix * (1.0 / WX_INVH);
+          const double d = X - Xg;
+          const double ef = exp(-d * (2.0 * Xg + d));
+          const double td = 2.0 * d;
+          const double *row = F.table + (int64_t)ix * F.nm - F.m_lo;
+          for (int m = mlo; m <= mhi; ++m) {
+            const double *r = row + m;
+            double sm = r[KT];
+#pragma unroll
+            for (int k = KT; k >= 1; --k) sm = fma(sm, td * (1.0 / k), r[k - 1]);
+            Om[m - mlo] = gp * ef * sm;
+            gp *= isq;
+          }
         }
       }
       double Z[LTOT_MAX + 1];
