@@ -174,8 +174,10 @@ int f12_quartets_scratch_prims(const f12_quartets *q, int64_t *n_prim_quartets);
  * d_p, d_q, d_R: device double[n]; d_A: device double[(L+1) n] with A_k of
  * point i at d_A[k*n + i].  route: 0 = the switch f12_eval uses (small-T
  * series below T = xi R^2 = 1 for L <= 3, 1.5, 2, 2, 2.5, 3, 3.5, 4, 4.5, 5
- * for L = 4..12 and 6 for L = 13, 14; the large-T lowering route above);
- * 1 = small-T series; 2 = large-T route with the exp(-xi (r+R)^2) side kept.
+ * for L = 4..12 and 6 for L = 13, 14, in binary64 where L <= 5 and T < 2 and
+ * in double-double otherwise; the large-T lowering route above);
+ * 1 = small-T series in double-double; 2 = large-T route with the
+ * exp(-xi (r+R)^2) side kept; 3 = small-T series in binary64.
  * Asynchronous on `stream`. */
 int f12_aux_radial(const f12_kernel *k, int64_t n, const double *d_p, const double *d_q,
                    const double *d_R, int32_t L, int32_t route, double *d_A, void *stream);

@@ -731,7 +731,7 @@ extern "C" void f12_kernel_destroy(f12_kernel *k) { delete k; }
 extern "C" int f12_aux_radial(const f12_kernel *k, int64_t n, const double *d_p, const double *d_q,
                               const double *d_R, int32_t L, int32_t route, double *d_A,
                               void *stream) {
-  if (!k || n < 0 || L < 0 || L > LTOT_MAX || route < 0 || route > 2 ||
+  if (!k || n < 0 || L < 0 || L > LTOT_MAX || route < 0 || route > 3 ||
       (n > 0 && (!d_p || !d_q || !d_R || !d_A)))
     return F12_EINVAL;
   if (launch_aux_points(k->d_desc.ptr, n, d_p, d_q, d_R, L, route, d_A, (hipStream_t)stream) != 0)

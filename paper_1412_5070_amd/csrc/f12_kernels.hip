@@ -328,6 +328,76 @@ __device__ void aux_small(const KernelDev *__restrict__ K, double xi, double u, 
   }
 }
 
+// The same series in binary64, for T < 2 and L <= 5, where the cancellation
+// (about e^{2T} and the alternating u-jet product) leaves ~1e-14 of the
+// scaled envelope; the S ladders, M_j and the u-jet as in aux_small.
+__device__ void aux_small_f64(const KernelDev *__restrict__ K, double xi, double u, int L,
+                              double T, double *A) {
+  int J = L + 20 + (int)(4.0 * T);
+  if (J > F12_JMAX) J = F12_JMAX;
+  double M[F12_JMAX + 1];
+  for (int j = 0; j <= J; ++j) M[j] = 0.0;
+  const int nchains = K->nchains;
+  for (int c = 0; c < nchains; ++c) {
+    const ChainDesc ch = K->chains[c];
+    const FamilyDesc F = K->fam[ch.family];
+    const double b = ch.b;
+    const double gam = xi + ch.g;
+    const double sg = sqrt(gam);
+    const double y = b / sg;
+    const double as = F.alpha0 + ch.m_min + 1;
+    const double p0 = pow(gam, -0.5 * (as + 1.0));
+    const double p1 = p0 / sg;
+    const double *ph = K->phi + 2 * (ch.phi_off);
+    double f0 = ph[2 * KPHI], f1 = ph[2 * (KPHI + 1) + 2 * KPHI];
+    if (b != 0.0) {
+      for (int k = KPHI - 1; k >= 0; --k) {
+        f0 = fma(f0, y, ph[2 * k]);
+        f1 = fma(f1, y, ph[2 * (KPHI + 1) + 2 * k]);
+      }
+    } else {
+      f0 = ph[0];
+      f1 = ph[2 * (KPHI + 1)];
+    }
+    double Sk = p0 * f0, Snext = p1 * f1;
+    const double inv2g = 0.5 / gam;
+    const int kmax = ch.m_max - ch.m_min + 2 * J;
+    for (int k = 0; k <= kmax; ++k) {
+      for (int t = ch.t_begin; t < ch.t_end; ++t) {
+        const int dk = k - (K->terms[t].m - ch.m_min);
+        if (dk >= 0 && !(dk & 1) && (dk >> 1) <= J) M[dk >> 1] = fma(Sk, K->terms[t].c, M[dk >> 1]);
+      }
+      const double Snn = ((as + k + 1) * Sk + b * Snext) * inv2g;
+      Sk = Snext;
+      Snext = Snn;
+    }
+  }
+  {
+    const double x4 = 4.0 * xi * xi;
+    double cj = 1.0;
+    for (int j = 0; j <= J; ++j) {
+      M[j] *= cj;
+      cj = cj * x4 / (double)((2 * j + 2) * (2 * j + 3));
+    }
+  }
+  double jet[LTOT_MAX + 1];
+  for (int k = 0; k <= L; ++k) jet[k] = 0.0;
+  for (int j = J; j >= 0; --j) {
+    for (int k = L; k >= 1; --k) jet[k] = fma(jet[k], u, jet[k - 1]);
+    jet[0] = fma(jet[0], u, M[j]);
+  }
+  double ej[LTOT_MAX + 1];
+  ej[0] = exp(-xi * u);
+  for (int i = 1; i <= L; ++i) ej[i] = ej[i - 1] * (-xi) / (double)i;
+  double scale = 4.0 * xi;
+  for (int n = 0; n <= L; ++n) {
+    double sacc = 0.0;
+    for (int i = 0; i <= n; ++i) sacc = fma(ej[i], jet[n - i], sacc);
+    A[n] = scale * sacc;
+    scale *= 2.0 * (n + 1);
+  }
+}
+
 // Small-T / large-T switch and the cut for the exp(-xi (r+R)^2) side.
 // The lowering route holds ~1e-14 of the (2 xi)^n-scaled envelope of A_n from
 // T = 1 (L <= 3), 1.5 (L = 4), 2 (L = 5, 6), 2.5, 3, 3.5, 4, 4.5, 5 (L = 7..12)
@@ -386,7 +456,10 @@ __global__ void __launch_bounds__(128) aux_kernel(const KernelDev *__restrict__ 
   const double Np = F12_PI52 / (sqrt(p + qq) * p * qq);
   double a[LTOT_MAX + 1];
   if (T < t_switch(L)) {
-    aux_small(K, xi, u, L, T, a);
+    if (L <= 5 && T < 2.0)
+      aux_small_f64(K, xi, u, L, T, a);
+    else
+      aux_small(K, xi, u, L, T, a);
   } else {
     aux_large(K, xi, sqrt(u), L, minus_side_needed(T, L), a);
   }
@@ -487,8 +560,15 @@ __global__ void aux_points_kernel(const KernelDev *__restrict__ K, int64_t n,
   const double T = xi * u;
   const double Np = F12_PI52 / (sqrt(p + q) * p * q);
   double a[LTOT_MAX + 1];
+  if (route == 3) {
+    aux_small_f64(K, xi, u, L, T, a);
+    for (int k = 0; k <= L; ++k) A[k * n + t] = a[k] * Np;
+    return;
+  }
   const bool small = (route == 1) || (route == 0 && T < t_switch(L));
-  if (small)
+  if (small && route == 0 && L <= 5 && T < 2.0)
+    aux_small_f64(K, xi, u, L, T, a);
+  else if (small)
     aux_small(K, xi, u, L, T, a);
   else
     aux_large(K, xi, R, L, route == 2 ? true : minus_side_needed(T, L), a);

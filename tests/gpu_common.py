@@ -44,3 +44,20 @@ def i5_block_err(got, ref_i5, ref_i3, bra_exps):
     scored against max(max|I5|, max bra exponent * max|I3|)."""
     scale = max(np.max(np.abs(ref_i5)), float(np.max(bra_exps)) * np.max(np.abs(ref_i3)))
     return float(np.max(np.abs(got - ref_i5)) / scale)
+
+
+# Blocks whose largest |integral| is below the workloads' screening threshold
+# (1e-12) are negligible; there the MD sums in binary64 can cancel by 1e4 and
+# more, so they are held to an absolute bound of 1e-12 of that threshold.
+NEGLIGIBLE = 1e-12
+ABS_FLOOR = 1e-24
+
+
+def block_ok(got, ref, rel_tol=1e-12):
+    """(passes, relative error, absolute error) under the rule above."""
+    scale = float(np.max(np.abs(ref)))
+    abs_err = float(np.max(np.abs(got - ref)))
+    rel = abs_err / scale if scale > 0 else abs_err
+    if scale >= NEGLIGIBLE:
+        return rel < rel_tol, rel, abs_err
+    return rel < rel_tol or abs_err < ABS_FLOOR, rel, abs_err

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 from synth import FACTOR_SETS, tiny_config
-from tests.gpu_common import block_rel_err, envelope_err, i5_block_err, run_quads
+from tests.gpu_common import block_ok, block_rel_err, envelope_err, i5_block_err, run_quads
 
 pytestmark = pytest.mark.gpu
 
@@ -83,6 +83,26 @@ def test_radial_routes_agree_in_overlap(lib):
             err = envelope_err(a2, a1, p * q / (p + q))
             print(f"overlap cls={cls} L={L} max {err.max():.2e}", flush=True)
             assert err.max() < 1e-13
+
+
+def test_radial_small_T_binary64_series(lib):
+    """The binary64 small-T series (used for L <= 5, T < 2) against the
+    double-double series."""
+    rng = np.random.default_rng(17)
+    for cls, fac in ((3, P1), (6, P1), (4, P1), (2, FACTOR_SETS["P4"])):
+        k = lib.Kernel(cls, fac, fac)
+        for L in range(0, 6):
+            pts = []
+            for T in (0.0, 1e-4, 0.3, 0.9, 1.4, 1.99):
+                for _ in range(6):
+                    p, q = 10 ** rng.uniform(-1.3, 2), 10 ** rng.uniform(-1.3, 2)
+                    pts.append((p, q, math.sqrt(T * (p + q) / (p * q))))
+            p, q, R = (np.array([x[j] for x in pts]) for j in range(3))
+            a1 = lib.aux_radial(k, p, q, R, L, route=1).cpu().numpy().T
+            a3 = lib.aux_radial(k, p, q, R, L, route=3).cpu().numpy().T
+            err = envelope_err(a3, a1, p * q / (p + q))
+            print(f"f64 series cls={cls} L={L} max {err.max():.2e}", flush=True)
+            assert err.max() < 3e-14
 
 
 @pytest.mark.parametrize("cls", [1, 3, 6])
@@ -206,8 +226,11 @@ def test_plain20_sampled_vs_golden(lib, cls):
         if cls == 5:
             ref3 = golden["c3_%d_%d_%d_%d" % tuple(qd)]
             e = i5_block_err(got, ref, ref3, np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps]))
+            ok = e < 1e-12 or (np.max(np.abs(ref3)) < 1e-12 and np.max(np.abs(got - ref)) < 1e-24)
+            ea = float(np.max(np.abs(got - ref)))
         else:
-            e = block_rel_err(got, ref)
+            ok, e, ea = block_ok(got, ref)
         worst = max(worst, e)
-        print(f"  {qd} l={[shells[j].l for j in qd]} err {e:.2e}", flush=True)
-        assert e < 1e-12, (qd, e)
+        note = "" if e < 1e-12 else " (negligible block: max|I| %.1e, abs err %.1e)" % (np.max(np.abs(ref)), ea)
+        print(f"  {qd} l={[shells[j].l for j in qd]} err {e:.2e}{note}", flush=True)
+        assert ok, (qd, e, ea)
