@@ -89,8 +89,9 @@ struct BigShape {
   static constexpr int NYT = (LP + 1) * (LAB + 1) * (LCD + 1);
   static constexpr int NEB = MODE == 2 ? max_eab2(BLAB) : (I5 ? 6 : 3) * max_eab(LAB);
   // LDS (doubles)
-  // per ket primitive of a pass: Z, Y, one-centre E
-  static constexpr int jZ = 0;
+  // per ket primitive of a pass: G rows, Z, Y, one-centre E
+  static constexpr int jG = 0;
+  static constexpr int jZ = jG + (L + 1) * (L + 1) + 2;
   static constexpr int jY = jZ + NLP * ZST;
   static constexpr int jEk = jY + (LP + 1) * YST;
   static constexpr int PJ = jEk + 3 * NE;
@@ -128,50 +129,74 @@ __device__ __forceinline__ void load_col(const double *p, int last, double (&c)[
 // d^T/dX^T of a function of |X|^2/2 (D = R^-1 d/dR); table [T][i], T <= 14.
 constexpr int HC_T = LTOT_MAX + 1, HC_I = LTOT_MAX / 2 + 1;
 
-// One Hermite line R_{T,U,w+SH}, w = 0..NW-1, of the primitive quartet, from
-//   R_{T,U,W} = sum_{i,j,k} c(T,i) X^(T-2i) c(U,j) Y^(U-2j) c(W,k) Z^(W-2k) A_{T+U+W-i-j-k},
-// the closed form of the recurrence R^(n)_{t+1,u,v} = t R^(n+1)_{t-1,u,v} +
-// X R^(n+1)_{tuv} (each d/dX of a radial function is X D).  Entries past the
-// line end (T + U + W > L) are 0.
-template <int L, int NW, int SH>
-__device__ __forceinline__ void r_line(int T, int U, double X, double Y, double Z, const double *A,
-                                       const double *hc, double (&R)[NW]) {
+// X-direction partial sums of the closed form below, one row per T:
+//   G_T[n] = sum_i c(T,i) X^(T-2i) A_{T-i+n},  n = 0..L-T  (row stride L+1).
+template <int L>
+__device__ __forceinline__ void g_row(int T, double X, const double *A, const double *hc, double *G) {
   constexpr int H = L / 2;
-  // col[m] = sum_{i,j} c(T,i) X^(T-2i) c(U,j) Y^(U-2j) A_{(T-i)+(U-j)+m}
-  double hx[H + 1], hy[H + 1];
+  double hx[H + 1];
   {
-    double px = (T & 1) ? X : 1.0, py = (U & 1) ? Y : 1.0;
-    const double X2 = X * X, Y2 = Y * Y;
+    double px = (T & 1) ? X : 1.0;
+    const double X2 = X * X;
 #pragma unroll
     for (int i = H; i >= 0; --i) {
       hx[i] = 0.0;
-      hy[i] = 0.0;
       if (2 * i <= T) {
         hx[i] = hc[T * HC_I + i] * px;
         px *= X2;
       }
+    }
+  }
+  const int rem = L - T;
+  double g[L + 1];
+#pragma unroll
+  for (int n = 0; n <= L; ++n) g[n] = 0.0;
+#pragma unroll
+  for (int i = 0; i <= H; ++i) {
+    if (2 * i > T) continue;
+    const double *Ap = A + (T - i);
+#pragma unroll
+    for (int n = 0; n <= L; ++n)
+      if (n <= rem) g[n] = fma(hx[i], Ap[n], g[n]);
+  }
+#pragma unroll
+  for (int n = 0; n <= L; ++n) G[n] = g[n];
+}
+
+// One Hermite line R_{T,U,w+SH}, w = 0..NW-1, of the primitive quartet, from
+//   R_{T,U,W} = sum_{i,j,k} c(T,i) X^(T-2i) c(U,j) Y^(U-2j) c(W,k) Z^(W-2k) A_{T+U+W-i-j-k},
+// the closed form of the recurrence R^(n)_{t+1,u,v} = t R^(n+1)_{t-1,u,v} +
+// X R^(n+1)_{tuv} (each d/dX of a radial function is X D), with the X sum
+// taken from the row G_T.  Entries past the line end (T + U + W > L) are 0.
+template <int L, int NW, int SH>
+__device__ __forceinline__ void r_line(int T, int U, double Y, double Z, const double *GT,
+                                       const double *hc, double (&R)[NW]) {
+  constexpr int H = L / 2;
+  double hy[H + 1];
+  {
+    double py = (U & 1) ? Y : 1.0;
+    const double Y2 = Y * Y;
+#pragma unroll
+    for (int i = H; i >= 0; --i) {
+      hy[i] = 0.0;
       if (2 * i <= U) {
         hy[i] = hc[U * HC_I + i] * py;
         py *= Y2;
       }
     }
   }
+  // col[m] = sum_j c(U,j) Y^(U-2j) G_T[U-j+m]
   const int rem = L - T - U;
   double col[L + 1];
 #pragma unroll
   for (int m = 0; m <= L; ++m) col[m] = 0.0;
 #pragma unroll
-  for (int i = 0; i <= H; ++i) {
-    if (2 * i > T) continue;
+  for (int j = 0; j <= H; ++j) {
+    if (2 * j > U) continue;
+    const double *Gp = GT + (U - j);
 #pragma unroll
-    for (int j = 0; j <= H; ++j) {
-      if (2 * j > U) continue;
-      const double w = hx[i] * hy[j];
-      const double *Ap = A + (T - i) + (U - j);
-#pragma unroll
-      for (int m = 0; m <= L; ++m)
-        if (m <= rem) col[m] = fma(w, Ap[m], col[m]);
-    }
+    for (int m = 0; m <= L; ++m)
+      if (m <= rem) col[m] = fma(hy[j], Gp[m], col[m]);
   }
   double zp[L + 1];
   zp[0] = 1.0;
@@ -371,27 +396,33 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
         // (T', U', sh) = (T, U, 0), the shifted line of an I5 component, or
         // the three terms of R_lap.
         const int nvj = nkc - jk0 < NJ ? nkc - jk0 : NJ;  // ket primitives in this pass
+        for (int k = tid; k < nvj * (L + 1); k += NT) {
+          const int jj = k / (L + 1), T = k - jj * (L + 1);
+          const int jk = jk0 + jj;
+          g_row<L>(T, KD[jk * S::KDW + 0] - Pb0, AS + jk * (L + 1), hc,
+                   lds + S::oRp + jj * S::PJ + S::jG + T * (L + 1));
+        }
+        __syncthreads();
         for (int k = tid; k < nvj * S::NLP; k += NT) {
           const int jj = k / S::NLP, line = k - jj * S::NLP;
           const int jk = jk0 + jj < nkc ? jk0 + jj : jk0;
-          const double X = KD[jk * S::KDW + 0] - Pb0, Y = KD[jk * S::KDW + 1] - Pb1,
-                       Zc = KD[jk * S::KDW + 2] - Pb2;
-          const double *Aj = AS + jk * (L + 1);
+          const double Y = KD[jk * S::KDW + 1] - Pb1, Zc = KD[jk * S::KDW + 2] - Pb2;
           double *base = lds + S::oRp + jj * S::PJ;
+          const double *G = base + S::jG;
           const int tu = linetu[line];
           const int T = tu & 255, U = tu >> 8;
           double rl[LP + 1];
           if (lap) {
             double r1[LP + 1], r2[LP + 1], r3[LP + 1];
-            r_line<L, LP + 1, 0>(T + 2, U, X, Y, Zc, Aj, hc, r1);
-            r_line<L, LP + 1, 0>(T, U + 2, X, Y, Zc, Aj, hc, r2);
-            r_line<L, LP + 1, 2>(T, U, X, Y, Zc, Aj, hc, r3);
+            r_line<L, LP + 1, 0>(T + 2, U, Y, Zc, G + (T + 2) * (L + 1), hc, r1);
+            r_line<L, LP + 1, 0>(T, U + 2, Y, Zc, G + T * (L + 1), hc, r2);
+            r_line<L, LP + 1, 2>(T, U, Y, Zc, G + T * (L + 1), hc, r3);
 #pragma unroll
             for (int w = 0; w <= LP; ++w) rl[w] = r1[w] + r2[w] + r3[w];
           } else if (dv) {
-            r_line<L, LP + 1, 1>(T, U, X, Y, Zc, Aj, hc, rl);
+            r_line<L, LP + 1, 1>(T, U, Y, Zc, G + T * (L + 1), hc, rl);
           } else {
-            r_line<L, LP + 1, 0>(T + dt, U + du, X, Y, Zc, Aj, hc, rl);
+            r_line<L, LP + 1, 0>(T + dt, U + du, Y, Zc, G + (T + dt) * (L + 1), hc, rl);
           }
           const double *ez = base + S::jEk + 2 * NE;
           double ezr[NE];

@@ -234,3 +234,45 @@ def test_plain20_sampled_vs_golden(lib, cls):
         note = "" if e < 1e-12 else " (negligible block: max|I| %.1e, abs err %.1e)" % (np.max(np.abs(ref)), ea)
         print(f"  {qd} l={[shells[j].l for j in qd]} err {e:.2e}{note}", flush=True)
         assert ok, (qd, e, ea)
+
+
+@pytest.mark.parametrize("cls", [3, 5])
+def test_schwarz_screening(lib, cls):
+    """f12_quartets_build with screen_tol keeps exactly the quartets with
+    Q_ab Q_cd >= tol, Q_ab = sqrt(max |(ab|k3|ab)|) (diagonal blocks evaluated
+    here through an explicit list), and kept blocks equal the unscreened ones."""
+    import os
+    import torch
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import df3_shells
+    shells = df3_shells()
+    basis = lib.Basis.from_shells(shells)
+    pairs = lib.Pairs(basis, 0)
+    k = lib.Kernel(cls, P1, P1)
+    k3 = lib.Kernel(3, P1, P1)
+    ns = len(shells)
+    upairs = [(i, j) for i in range(ns) for j in range(i + 1)]
+    diag = [(i, j, i, j) for (i, j) in upairs]
+    got = run_quads(lib, basis, lib.Pairs(basis, 1), k3, 3, diag)
+    Qab = {(i, j): math.sqrt(float(np.max(np.abs(got[(i, j, i, j)])))) for (i, j) in upairs}
+    prods = sorted(Qab[p] * Qab[q] for p in upairs for q in upairs)
+    tol = prods[len(prods) // 3]
+    full = lib.Quartets.build(pairs, pairs, cls)
+    scr = lib.Quartets.build(pairs, pairs, cls, screen_tol=tol, screen_kernel=k3)
+    fq = [tuple(int(v) for v in r) for r in full.quads()]
+    sq = [tuple(int(v) for v in r) for r in scr.quads()]
+    expect = [q for q in fq if Qab[(q[0], q[1])] * Qab[(q[2], q[3])] >= tol]
+    print(f"screening cls={cls} tol={tol:.3e} full={len(fq)} kept={len(sq)}", flush=True)
+    assert sq == expect
+    assert 0 < len(sq) < len(fq)
+    out_f = torch.empty(full.n_out, dtype=torch.float64, device="cuda")
+    out_s = torch.empty(scr.n_out, dtype=torch.float64, device="cuda")
+    lib.eval_into(full, k, out_f)
+    lib.eval_into(scr, k, out_s)
+    lib.stream_status()
+    hf, hs = out_f.cpu().numpy(), out_s.cpu().numpy()
+    of, os_ = full.offsets(), scr.offsets()
+    pos = {q: i for i, q in enumerate(fq)}
+    for i, q in enumerate(sq):
+        j = pos[q]
+        assert np.array_equal(hs[os_[i]:os_[i + 1]], hf[of[j]:of[j + 1]]), q
