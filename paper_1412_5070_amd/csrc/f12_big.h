@@ -245,13 +245,16 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
     const int t = N - s;
     tuv[idx] = t | (u << 8) | ((N - t - u) << 16);
   }
+  // line tasks ordered by T + U, longest-first groups of equal length, so
+  // that a wave's lanes share their line length (dead code is skipped whole)
   for (int line = tid; line < S::NLP; line += NT) {
-    int T = 0, base = 0;
-    while (base + (LP + 1 - T) <= line) {
-      base += LP + 1 - T;
-      ++T;
+    int Ssum = LP, base = 0;
+    while (base + (Ssum + 1) <= line) {
+      base += Ssum + 1;
+      --Ssum;
     }
-    linetu[line] = T | ((line - base) << 8);
+    const int T = line - base;
+    linetu[line] = T | ((Ssum - T) << 8);
   }
   double *hc = lds + S::oHC;
   for (int w = tid; w < HC_T * HC_I; w += NT) {
@@ -411,6 +414,7 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
           const double *G = base + S::jG;
           const int tu = linetu[line];
           const int T = tu & 255, U = tu >> 8;
+          const int zline = T * (LP + 1) - T * (T - 1) / 2 + U;  // storage order: T, then U
           double rl[LP + 1];
           if (lap) {
             double r1[LP + 1], r2[LP + 1], r3[LP + 1];
@@ -428,7 +432,7 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
           double ezr[NE];
 #pragma unroll
           for (int e = 0; e < NE; ++e) ezr[e] = ez[e];
-          double *zo = base + S::jZ + line * S::ZST;
+          double *zo = base + S::jZ + zline * S::ZST;
 #pragma unroll
           for (int v = 0; v <= LAB; ++v) {
 #pragma unroll
@@ -451,9 +455,10 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
 #pragma unroll
           for (int k = 0; k < NE; ++k) ey[k] = base[S::jEk + NE + k];
           for (int k = tid; k < S::NYT; k += NT) {
-            const int fz = k % (LCD + 1);
-            const int r1 = k / (LCD + 1);
-            const int v = r1 % (LAB + 1), T = r1 / (LAB + 1);
+            // T fastest: the lanes of a wave share (v, fz) in runs
+            const int T = k % (LP + 1);
+            const int r1 = k / (LP + 1);
+            const int v = r1 % (LAB + 1), fz = r1 / (LAB + 1);
             if (T + v + fz > LP) continue;
             const int line0 = T * (LP + 1) - T * (T - 1) / 2;
             double col[LP + 1];
