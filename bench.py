@@ -5,9 +5,11 @@ One step evaluates one batch of the 20-atom molecule's unique shell quartets
 log-uniform in [0.05, 50]; factor set P1) for every class I2-I6: radial
 derivatives of the basic integrals, Hermite integrals, E.R.E contraction,
 contracted blocks written to an HBM ring buffer.  The quartet list of each
-class is split into --batches stratified batches (the b-th slice of every
-(l_a, l_b, l_c, l_d) group), so successive steps cover different quartets and
---batches steps cover the whole job.  Inputs are resident in HBM before the
+class is split into --batches batches: batch b takes slice (b + g) mod
+batches of the g-th (l_a, l_b, l_c, l_d) group (groups are ordered by
+decreasing primitive count), so each step mixes heavy and light slices,
+successive steps cover different quartets and --batches steps cover the
+whole job.  Inputs are resident in HBM before the
 timed region.
 
 Prints one JSON line: contracted quartets/s over the timed steps (all
@@ -196,10 +198,14 @@ def main():
     ring_pos = [0]
 
     def slices(wk, batch):
-        for (a, b, lq) in wk["groups"]:
+        # groups are ordered by decreasing primitive count, so batch b takes
+        # slice (b + g) mod batches of group g: every step mixes heavy and
+        # light slices
+        for g, (a, b, lq) in enumerate(wk["groups"]):
             n = b - a
-            s0 = a + (n * batch) // args.batches
-            s1 = a + (n * (batch + 1)) // args.batches
+            sl = (batch + g) % args.batches
+            s0 = a + (n * sl) // args.batches
+            s1 = a + (n * (sl + 1)) // args.batches
             while s0 < s1:
                 # split so that a slice's primitive quartets fit the scratch
                 hi = int(np.searchsorted(wk["cprim"], wk["cprim"][s0] + wk["cap"], side="right")) - 1

@@ -124,13 +124,15 @@ void f12_kernel_destroy(f12_kernel *k);
  * Q_ab = sqrt(max |(ab|k|ab)|) evaluated with `screen_kernel` (use an I3
  * kernel for I5); screen_kernel may be NULL when screen_tol <= 0.
  * The public order (offsets, output, f12_quartet_list) groups the quartets
- * by (l_a, l_b, l_c, l_d) and keeps the enumeration order inside a group. */
+ * by (l_a, l_b, l_c, l_d) and, inside a group, orders them by decreasing
+ * number of primitive quartets (enumeration order among equal counts). */
 int f12_quartets_build(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
                        double screen_tol, const f12_kernel *screen_kernel, void *stream,
                        f12_quartets **out, int64_t *n_quartets, int64_t *n_out_doubles);
 /* An explicit list of nq shell quadruples (a, b, c, d) (host int32[4*nq]);
  * bra and ket must be ordered pair sets.  The public order groups the list
- * by (l_a, l_b, l_c, l_d) (stable): read it back with f12_quartet_list. */
+ * by (l_a, l_b, l_c, l_d) and by decreasing primitive count inside a group
+ * (stable): read it back with f12_quartet_list. */
 int f12_quartets_from_list(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
                            const int32_t *shell_quads, int64_t nq, f12_quartets **out,
                            int64_t *n_out_doubles);

@@ -766,6 +766,29 @@ int finish_quartets(f12_quartets *Q, std::vector<int64_t> &qb, std::vector<int64
   qb.shrink_to_fit();
   qk.clear();
   qk.shrink_to_fit();
+  // inside each group: decreasing primitive-quartet count (stable), so that
+  // the longest work-groups of a launch start first
+  {
+    std::vector<int64_t> idx, tb, tk;
+    for (int k = 0; k < 256; ++k) {
+      const int64_t lo = cnt[k], n = cnt[k + 1] - cnt[k];
+      if (n < 2) continue;
+      idx.resize(n);
+      for (int64_t i = 0; i < n; ++i) idx[i] = lo + i;
+      auto np = [&](int64_t i) {
+        return (int64_t)B->ka[Q->qb[i]] * B->kb[Q->qb[i]] * (int64_t)K->ka[Q->qk[i]] * K->kb[Q->qk[i]];
+      };
+      std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return np(x) > np(y); });
+      tb.resize(n);
+      tk.resize(n);
+      for (int64_t i = 0; i < n; ++i) {
+        tb[i] = Q->qb[idx[i]];
+        tk[i] = Q->qk[idx[i]];
+      }
+      std::copy(tb.begin(), tb.end(), Q->qb.begin() + lo);
+      std::copy(tk.begin(), tk.end(), Q->qk.begin() + lo);
+    }
+  }
   Q->bins.clear();
   for (int k = 0; k < 256; ++k) {
     int64_t n = cnt[k + 1] - cnt[k];
