@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--batches", type=int, default=16)
     ap.add_argument("--classes", default=",".join(str(c) for c in CLASSES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--concurrent", action="store_true",
+                    help="one stream per class, classes run concurrently (per-class rates then overlap)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the integral path has no multi-GPU mode; use --gpus 1",
@@ -194,8 +196,13 @@ def main():
                          cap=cap, nq=len(key), quads=quads if cls == 3 else None))
         log("I%d: %d quartets in %d groups" % (cls, len(key), len(groups)))
 
-    ring = torch.empty(1 << 28, dtype=torch.float64, device="cuda")  # 2 GiB output ring
-    ring_pos = [0]
+    # output rings in HBM, one per class (each class's stream writes its own)
+    ring_all = torch.empty(1 << 28, dtype=torch.float64, device="cuda")  # 2 GiB
+    per = ring_all.numel() // len(work)
+    for i, wk in enumerate(work):
+        wk["ring"] = ring_all[i * per:(i + 1) * per]
+        wk["ring_pos"] = 0
+        wk["stream"] = torch.cuda.Stream() if args.concurrent else stream
 
     def slices(wk, batch):
         # groups are ordered by decreasing primitive count, so batch b takes
@@ -214,26 +221,31 @@ def main():
                 s0 = e
 
     def run_step(batch, record):
+        start = torch.cuda.Event()
+        start.record(stream)
         for wk in work:
             Q, kern, offs = wk["Q"], wk["kern"], wk["offs"]
+            st = wk["stream"]
+            st.wait_event(start)
             ev_cls0 = torch.cuda.Event(enable_timing=True)
             ev_cls1 = torch.cuda.Event(enable_timing=True)
-            ev_cls0.record(stream)
+            ev_cls0.record(st)
             nq = 0
+            ring = wk["ring"]
             for (s0, s1, lq) in slices(wk, batch):
                 size = int(offs[s1] - offs[s0])
-                if ring_pos[0] + size > ring.numel():
-                    ring_pos[0] = 0
-                out = ring[ring_pos[0]:ring_pos[0] + size]
-                ring_pos[0] += size
+                if wk["ring_pos"] + size > ring.numel():
+                    wk["ring_pos"] = 0
+                out = ring[wk["ring_pos"]:wk["ring_pos"] + size]
+                wk["ring_pos"] += size
                 ea = torch.cuda.Event(enable_timing=True)
-                ea.record(stream)
-                f12int.eval_stage(Q, kern, out, s0, s1, 1, stream)
+                ea.record(st)
+                f12int.eval_stage(Q, kern, out, s0, s1, 1, st)
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                f12int.eval_stage(Q, kern, out, s0, s1, 2, stream)
-                e1.record(stream)
+                e0.record(st)
+                f12int.eval_stage(Q, kern, out, s0, s1, 2, st)
+                e1.record(st)
                 if record is not None:
                     record["aux"].append((ea, e0))
                 nq += s1 - s0
@@ -243,11 +255,14 @@ def main():
                     fl = contraction_flops(la, lb, lc, ld, i5, int(wk["cprim"][s1] - wk["cprim"][s0]),
                                            int(wk["cbra"][s1] - wk["cbra"][s0]), s1 - s0)
                     record["launches"].append((kernel_name(la, lb, lc, ld, i5), fl, e0, e1))
-            ev_cls1.record(stream)
+            ev_cls1.record(st)
             if record is not None:
                 record["classes"].append((wk["cls"], nq, ev_cls0, ev_cls1))
-            torch.cuda.synchronize()
-            log("batch %d I%d: %d quartets done" % (batch, wk["cls"], nq))
+            if not args.concurrent:
+                torch.cuda.synchronize()
+                log("batch %d I%d: %d quartets done" % (batch, wk["cls"], nq))
+        torch.cuda.synchronize()
+        log("batch %d: all classes done" % batch)
 
     for w in range(args.warmup):
         run_step(w % args.batches, None)
@@ -315,6 +330,7 @@ def main():
                         "primitives, all unique quartets of I2-I6 (factor P1), one of %d stratified "
                         "batches per step" % args.batches,
             "classes": ["I%d" % c for c in classes],
+            "streams": "one per class, concurrent (per-class rates overlap)" if args.concurrent else "one",
             "quartets_per_step": nq_total // max(args.steps, 1),
         },
         "per_class_quartets_per_s": per_class_rate,
