@@ -149,6 +149,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--concurrent", action="store_true",
                     help="one stream per class, classes run concurrently (per-class rates then overlap)")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="run the next slice's radial derivatives on a second stream while the current "
+                         "slice contracts (launch timings then overlap)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the integral path has no multi-GPU mode; use --gpus 1",
@@ -192,7 +195,10 @@ def main():
             a, b = int(starts[g]), int(starts[g + 1])
             la, lb, lc, ld = (int(ls[quads[a, i]]) for i in range(4))
             groups.append((a, b, (la, lb, lc, ld)))
-        work.append(dict(cls=cls, kern=kern, Q=Q, offs=offs, groups=groups, cprim=cprim, cbra=cbra,
+        # a second copy of the list owns a second radial-derivative scratch, so
+        # that slice s+1's derivatives can run while slice s contracts
+        Q2 = f12int.Quartets.build(pairs, pairs, cls) if args.pipeline else None
+        work.append(dict(cls=cls, kern=kern, Q=Q, Q2=Q2, offs=offs, groups=groups, cprim=cprim, cbra=cbra,
                          cap=cap, nq=len(key), quads=quads if cls == 3 else None))
         log("I%d: %d quartets in %d groups" % (cls, len(key), len(groups)))
 
@@ -203,6 +209,7 @@ def main():
         wk["ring"] = ring_all[i * per:(i + 1) * per]
         wk["ring_pos"] = 0
         wk["stream"] = torch.cuda.Stream() if args.concurrent else stream
+        wk["aux_stream"] = torch.cuda.Stream() if args.pipeline else wk["stream"]
 
     def slices(wk, batch):
         # groups are ordered by decreasing primitive count, so batch b takes
@@ -232,22 +239,33 @@ def main():
             ev_cls0.record(st)
             nq = 0
             ring = wk["ring"]
-            for (s0, s1, lq) in slices(wk, batch):
+            sa = wk["aux_stream"]
+            sa.wait_event(ev_cls0)
+            done = [None, None]  # last contraction that read each list's scratch
+            for i, (s0, s1, lq) in enumerate(slices(wk, batch)):
                 size = int(offs[s1] - offs[s0])
                 if wk["ring_pos"] + size > ring.numel():
                     wk["ring_pos"] = 0
                 out = ring[wk["ring_pos"]:wk["ring_pos"] + size]
                 wk["ring_pos"] += size
+                Qi = Q if (wk["Q2"] is None or i % 2 == 0) else wk["Q2"]
+                if done[i % 2] is not None and sa is not st:
+                    sa.wait_event(done[i % 2])
                 ea = torch.cuda.Event(enable_timing=True)
-                ea.record(st)
-                f12int.eval_stage(Q, kern, out, s0, s1, 1, st)
+                ea_end = torch.cuda.Event(enable_timing=True)
+                ea.record(sa)
+                f12int.eval_stage(Qi, kern, out, s0, s1, 1, sa)
+                ea_end.record(sa)
+                if sa is not st:
+                    st.wait_event(ea_end)
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(st)
-                f12int.eval_stage(Q, kern, out, s0, s1, 2, st)
+                f12int.eval_stage(Qi, kern, out, s0, s1, 2, st)
                 e1.record(st)
+                done[i % 2] = e1
                 if record is not None:
-                    record["aux"].append((ea, e0))
+                    record["aux"].append((ea, ea_end))
                 nq += s1 - s0
                 if record is not None:
                     la, lb, lc, ld = lq
@@ -330,7 +348,8 @@ def main():
                         "primitives, all unique quartets of I2-I6 (factor P1), one of %d stratified "
                         "batches per step" % args.batches,
             "classes": ["I%d" % c for c in classes],
-            "streams": "one per class, concurrent (per-class rates overlap)" if args.concurrent else "one",
+            "streams": ("one per class, concurrent (per-class rates overlap)" if args.concurrent else "one")
+                       + ("; radial derivatives of the next slice overlap the contraction" if args.pipeline else ""),
             "quartets_per_step": nq_total // max(args.steps, 1),
         },
         "per_class_quartets_per_s": per_class_rate,

@@ -41,8 +41,10 @@ typedef enum {
   F12_OK = 0,
   F12_EINVAL = -1,    /* bad argument (null pointer, out-of-range index, ...)   */
   F12_EPARAM = -2,    /* factor parameters rejected (mu <= 0, non-finite, n   */
-                      /* violating n > -rho/2 - 1 for rho < -2, or a negative   */
-                      /* integer power in the kernel: not supported)           */
+                      /* violating n > -rho/2 - 1 for rho < -2, or a kernel     */
+                      /* term the library does not support: a negative integer  */
+                      /* power, a power <= -2, b < 0, or too many terms/chains  */
+                      /* or too wide a range of powers in one chain)           */
   F12_ELMAX = -3,     /* angular momentum above the supported maximum           */
   F12_ENOMEM = -4,    /* host or device allocation failed                       */
   F12_EDEVICE = -5,   /* a HIP runtime call failed                              */

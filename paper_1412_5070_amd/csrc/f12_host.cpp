@@ -652,6 +652,8 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
       cd.m_max = std::max(cd.m_max, pr.first);
     }
     cd.t_end = nt;
+    // the large-T route keeps W of orders m_min - L .. m_max per chain
+    if (cd.m_max - cd.m_min + LTOT_MAX + 1 > NW_MAX) return F12_EPARAM;
     cd.phi_off = (int)c * 2 * (KPHI + 1);
     Fam &F = fams[cd.family];
     int lo = F.is_int ? 0 : cd.m_min - LTOT_MAX;

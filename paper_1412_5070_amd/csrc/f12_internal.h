@@ -12,6 +12,8 @@ constexpr int MAX_TERMS = 96;
 constexpr int MAX_FAMILIES = 4;
 constexpr int KT = 16;                  // Taylor terms of the W-table interpolation
 constexpr int KPHI = 96;                // terms of the DD Phi-series (small-T route)
+constexpr int NW_MAX = 64;              // orders of W per chain in the large-T route:
+                                        // (m_max - m_min) + LTOT_MAX + 1 must not exceed it
 constexpr double WX_LO = -10.5;         // W-table abscissa range
 constexpr double WX_HI = 36.0;
 constexpr double WX_INVH = 64.0;        // grid step 1/64

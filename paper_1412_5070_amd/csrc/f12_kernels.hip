@@ -83,7 +83,7 @@ __device__ double w_asym(double a, double X) {
 // H-recursion of Eq. (finalrec), which cancels like (2T)^n/(2n-1)!! in
 // binary64).  D^n(phi/R) is then formed from the R-jet of phi.
 // ---------------------------------------------------------------------------
-#define F12_NW 64
+#define F12_NW NW_MAX
 
 __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, int L,
                           bool do_minus, double *A) {
