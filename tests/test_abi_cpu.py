@@ -87,3 +87,15 @@ def test_aux_table_builder_vs_parabolic_cylinder(alpha0, is_int, m_lo, m_hi, x):
         for i, m in enumerate(range(m_lo, m_hi + 1)):
             ref = _w_ref(alpha0 + m, x)
             assert abs(col[i] - ref) <= 3e-16 * abs(ref), (m, col[i], ref)
+
+
+def test_unsupported_kernel_terms_rejected_before_device():
+    """Kernel terms the library does not evaluate return F12_EPARAM during
+    term analysis, before any device work: negative integer powers (factor
+    set P3 with rho = -3) and growing chains with b < 0 (B < 0)."""
+    from paper_1412_5070_amd import f12int
+    from synth import FACTOR_SETS, Factor
+    for cls, f in ((3, FACTOR_SETS["P3"]), (2, FACTOR_SETS["P3"]), (3, Factor(0.2, 0.5, -0.3, 0.8, 0))):
+        with pytest.raises(f12int.F12Error) as e:
+            f12int.Kernel(cls, f, f)
+        assert e.value.status == -2
