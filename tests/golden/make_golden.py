@@ -11,6 +11,8 @@ Sets:
            quartets that span every contraction path (same-centre (ff|ff)
            with R = 0, multi-centre (ff|ff), (dd|dd), mixed l, (ss|ff) and
            (ff|ss)), classes I1-I6 with the factor set P1.
+  deep     deep contractions: 36 and 256 ket primitive pairs and a
+           16-primitive bra shell (s and p shells); I3, I5, I6 with P1.
   plain20  quartets sampled from the 20-atom molecule (seed 5070), stratified
            by total angular momentum, restricted to at most 64 primitive
            quartets so that the oracle finishes; classes I2-I6, P1.
@@ -42,6 +44,25 @@ DF3_QUADS_I5 = [(3, 2, 6, 5), (2, 3, 6, 5), (7, 11, 1, 0), (0, 0, 11, 7), (6, 2,
                 (2, 2, 9, 4), (3, 2, 7, 11)]
 
 
+def deep_shells():
+    """Five shells at seeded positions in a 3 bohr cube: p(16), s(2), s(6),
+    p(6), s(16) primitives, exponents log-uniform in [0.1, 10]."""
+    from synth.molecules import Shell
+    ls, Ks = [1, 0, 0, 1, 0], [16, 2, 6, 6, 16]
+    rng = np.random.default_rng(4242)
+    pos = rng.uniform(0.0, 3.0, (len(ls), 3))
+    out = []
+    for i, (l, K) in enumerate(zip(ls, Ks)):
+        ex = 10.0 ** rng.uniform(-1.0, 1.0, K)
+        co = rng.uniform(0.1, 1.0, K)
+        out.append(Shell(pos[i], l, ex, co, i))
+    return out
+
+
+# (s2 s2|s6 p6): 36 ket primitive pairs; (s2 s2|s16 s16): 256; (p16 s2|s6 s6): 16-primitive bra shell
+DEEP_QUADS = [(1, 1, 2, 3), (1, 1, 4, 4), (0, 1, 2, 2)]
+
+
 def plain20_quads(n_per_L=2, max_prim=64, seed=99):
     _, shells = config_plain()
     ls = np.array([s.l for s in shells])
@@ -70,7 +91,7 @@ def plain20_quads(n_per_L=2, max_prim=64, seed=99):
 
 def _job(args):
     setname, cls, quad = args
-    shells = df3_shells() if setname == "df3" else config_plain()[1]
+    shells = {"df3": df3_shells, "deep": deep_shells}.get(setname, lambda: config_plain()[1])()
     sh = [shells[i].as_dict() for i in quad]
     return args, np.asarray(integrals.contracted(cls, *sh, P1, P1), dtype=np.float64).ravel()
 
@@ -80,6 +101,8 @@ def build(setname):
         jobs = [(setname, c, q) for c in (1, 2, 3, 4, 6) for q in DF3_QUADS]
         jobs += [(setname, 5, q) for q in DF3_QUADS_I5]
         jobs += [(setname, 3, q) for q in DF3_QUADS_I5 if q not in DF3_QUADS]
+    elif setname == "deep":
+        jobs = [(setname, c, q) for c in (5, 3, 6) for q in DEEP_QUADS]
     else:
         quads = plain20_quads()
         jobs = [(setname, c, q) for c in (5, 2, 3, 4, 6) for q in quads]
@@ -92,5 +115,5 @@ def build(setname):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or ["df3", "plain20"]):
+    for name in (sys.argv[1:] or ["df3", "deep", "plain20"]):
         build(name)

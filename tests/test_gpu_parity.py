@@ -276,3 +276,38 @@ def test_schwarz_screening(lib, cls):
     for i, q in enumerate(sq):
         j = pos[q]
         assert np.array_equal(hs[os_[i]:os_[i + 1]], hf[of[j]:of[j + 1]]), q
+
+
+@pytest.mark.parametrize("cls", [3, 5, 6])
+def test_deep_contractions_vs_golden(lib, cls):
+    """Deep contractions: 36 and 256 ket primitive pairs (several staging
+    chunks of ket primitives) and a 16-primitive bra shell (the ABI maximum)."""
+    import os
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import DEEP_QUADS, deep_shells
+    _check_golden_set(lib, deep_shells(), _golden("deep"), cls, DEEP_QUADS)
+
+
+def test_eval_error_paths(lib):
+    """Argument errors are reported before any launch: short output buffer,
+    class mismatch, stage 2 without stage 1, empty range."""
+    import torch
+    shells = _tiny()
+    basis = lib.Basis.from_shells(shells)
+    pairs = lib.Pairs(basis, 0)
+    k3, k2 = lib.Kernel(3, P1, P1), lib.Kernel(2, P1, P1)
+    Q = lib.Quartets.build(pairs, pairs, 3)
+    offs = Q.offsets()
+    short = torch.empty(int(offs[2] - offs[0]) - 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.F12Error) as e:
+        lib.eval_into(Q, k3, short, 0, 2)
+    assert e.value.status == -6
+    buf = torch.empty(int(offs[-1]), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.F12Error) as e:
+        lib.eval_into(Q, k2, buf)
+    assert e.value.status == -1
+    with pytest.raises(lib.F12Error) as e:
+        lib.eval_stage(Q, k3, buf, 0, 1, 2)
+    assert e.value.status == -1
+    lib.eval_into(Q, k3, buf, 3, 3)  # empty range: nothing to do
+    lib.stream_status()
