@@ -419,43 +419,88 @@ __device__ __forceinline__ bool minus_side_needed(double T, int L) {
 }
 
 // ---------------------------------------------------------------------------
-// K3/K4: one thread per primitive quartet of a chunk; A[n * np + t] = A_n.
+// K3/K4: A[n * np + t] = A_n for the primitive quartets of a chunk.  Each
+// work-group takes F12_NT_AUX consecutive primitive quartets, computes their
+// geometry and T, and hands them out again ordered by route and by octave of
+// T (a counting sort in LDS), so that the lanes of a wave mostly take the
+// same branch.  Each result is still written to its own slot and does not
+// depend on which thread computes it.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(128) aux_kernel(const KernelDev *__restrict__ K, PairsDev bra,
+#ifndef F12_NT_AUX
+#define F12_NT_AUX 512
+#endif
+constexpr int AUX_BINS = 16;
+
+__device__ __forceinline__ int aux_bin(double T, int L, double sw) {
+  if (T < sw) return (L <= 5 && T < 2.0) ? 0 : 1;
+  int e = ilogb(T / sw);  // octave above the switch; NaN and inf are clamped
+  e = e < 0 ? 0 : (e > AUX_BINS - 3 ? AUX_BINS - 3 : e);
+  return 2 + e;
+}
+
+__global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__restrict__ K, PairsDev bra,
                                                   PairsDev ket, const int64_t *__restrict__ qb,
                                                   const int64_t *__restrict__ qk,
                                                   const int64_t *__restrict__ qprim, int64_t qa,
                                                   int64_t nqc, int64_t p0, int64_t np, int L,
                                                   double *__restrict__ A) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= np) return;
-  const int64_t gidx = p0 + t;
-  int64_t lo = qa, hi = qa + nqc;
-  while (hi - lo > 1) {
-    int64_t mid = (lo + hi) >> 1;
-    if (qprim[mid] <= gidx)
-      lo = mid;
-    else
-      hi = mid;
+  __shared__ double s_xi[F12_NT_AUX], s_u[F12_NT_AUX], s_np[F12_NT_AUX];
+  __shared__ int s_perm[F12_NT_AUX];
+  __shared__ int s_cnt[AUX_BINS], s_off[AUX_BINS];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * F12_NT_AUX;
+  const int64_t t = base + tid;
+  const double sw = t_switch(L);
+  if (tid < AUX_BINS) s_cnt[tid] = 0;
+  __syncthreads();
+  int bin = AUX_BINS - 1;
+  if (t < np) {
+    const int64_t gidx = p0 + t;
+    int64_t lo = qa, hi = qa + nqc;
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if (qprim[mid] <= gidx)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int64_t q = lo;
+    const int64_t local = gidx - qprim[q];
+    const int64_t bp = qb[q], kp = qk[q];
+    const int64_t nk = (int64_t)ket.ka[kp] * ket.kb[kp];
+    const int64_t i = local / nk;
+    const int64_t j = local - i * nk;
+    const int64_t ib = bra.pp_off[bp] + i;
+    const int64_t ik = ket.pp_off[kp] + j;
+    const double p = bra.p[ib], qq = ket.p[ik];
+    const double X = ket.Px[ik] - bra.Px[ib];
+    const double Y = ket.Py[ik] - bra.Py[ib];
+    const double Z = ket.Pz[ik] - bra.Pz[ib];
+    const double u = X * X + Y * Y + Z * Z;
+    const double xi = p * qq / (p + qq);
+    s_xi[tid] = xi;
+    s_u[tid] = u;
+    s_np[tid] = F12_PI52 / (sqrt(p + qq) * p * qq);
+    bin = aux_bin(xi * u, L, sw);
   }
-  const int64_t q = lo;
-  const int64_t local = gidx - qprim[q];
-  const int64_t bp = qb[q], kp = qk[q];
-  const int64_t nk = (int64_t)ket.ka[kp] * ket.kb[kp];
-  const int64_t i = local / nk;
-  const int64_t j = local - i * nk;
-  const int64_t ib = bra.pp_off[bp] + i;
-  const int64_t ik = ket.pp_off[kp] + j;
-  const double p = bra.p[ib], qq = ket.p[ik];
-  const double X = ket.Px[ik] - bra.Px[ib];
-  const double Y = ket.Py[ik] - bra.Py[ib];
-  const double Z = ket.Pz[ik] - bra.Pz[ib];
-  const double u = X * X + Y * Y + Z * Z;
-  const double xi = p * qq / (p + qq);
+  const int rank = atomicAdd(&s_cnt[bin], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int s = 0;
+    for (int b = 0; b < AUX_BINS; ++b) {
+      s_off[b] = s;
+      s += s_cnt[b];
+    }
+  }
+  __syncthreads();
+  s_perm[s_off[bin] + rank] = tid;
+  __syncthreads();
+  const int me = s_perm[tid];
+  if (base + me >= np) return;
+  const double xi = s_xi[me], u = s_u[me], Np = s_np[me];
   const double T = xi * u;
-  const double Np = F12_PI52 / (sqrt(p + qq) * p * qq);
   double a[LTOT_MAX + 1];
-  if (T < t_switch(L)) {
+  if (T < sw) {
     if (L <= 5 && T < 2.0)
       aux_small_f64(K, xi, u, L, T, a);
     else
@@ -463,7 +508,7 @@ __global__ void __launch_bounds__(128) aux_kernel(const KernelDev *__restrict__ 
   } else {
     aux_large(K, xi, sqrt(u), L, minus_side_needed(T, L), a);
   }
-  for (int n = 0; n <= L; ++n) A[n * np + t] = a[n] * Np;
+  for (int n = 0; n <= L; ++n) A[n * np + base + me] = a[n] * Np;
 }
 
 
@@ -493,9 +538,8 @@ int launch_aux(const KernelDev *K, const PairsDev &bra, const PairsDev &ket, con
                const int64_t *qk, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
                int64_t np, int L, double *A, hipStream_t stream) {
   if (np <= 0) return 0;
-  int nt = 128;
-  int64_t nbk = (np + nt - 1) / nt;
-  hipLaunchKernelGGL(aux_kernel, dim3((unsigned)nbk), dim3(nt), 0, stream, K, bra, ket, qb, qk,
+  const int64_t nbk = (np + F12_NT_AUX - 1) / F12_NT_AUX;
+  hipLaunchKernelGGL(aux_kernel, dim3((unsigned)nbk), dim3(F12_NT_AUX), 0, stream, K, bra, ket, qb, qk,
                      qprim, qa, nqc, p0, np, L, A);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
