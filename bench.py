@@ -103,10 +103,8 @@ def contraction_flops(la, lb, lc, ld, i5, n_prim, n_bra_prim, n_quartets):
 
 
 def kernel_name(la, lb, lc, ld, i5):
-    Lab, Lcd = la + lb, lc + ld
-    if Lab + Lcd + (2 if i5 else 0) > 4:
-        return "big_kernel<%d, %d, %s>" % (Lab, Lcd, "true" if i5 else "false")
-    return "contract_kernel<L=%d%s>" % (Lab + Lcd, ", I5" if i5 else "")
+    """The big_kernel instantiation family of a shell-quartet shape."""
+    return "big_kernel, l_a+l_b=%d, l_c+l_d=%d%s" % (la + lb, lc + ld, ", I5" if i5 else "")
 
 
 # ---------------------------------------------------------------------------
@@ -354,7 +352,7 @@ def main():
         },
         "per_class_quartets_per_s": per_class_rate,
         "roofline": {
-            "kernel": "E.R.E contraction (big_kernel<*>, contract_kernel<*>)",
+            "kernel": "E.R.E contraction (big_kernel<*>)",
             "bound": "alu",
             "achieved": achieved,
             "peak": FP64_VECTOR_PEAK_TFLOPS,
