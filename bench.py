@@ -19,6 +19,7 @@ launch time, both measured here with HIP events on the launch stream), and
 the CPU oracle's rate on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -33,6 +34,32 @@ sys.path.insert(0, ROOT)
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 flop/clk)
 CLASSES = (2, 3, 4, 5, 6)
 METRIC = "contracted shell-quartets/s per F12 class at ≤1e-12 rel err; % FP64 peak"
+
+# HBM traffic per launch of the contraction and radial-derivative kernels,
+# from two rocprofv3 --pmc passes over this script's default run (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch, averaged over the launches of the timed
+# steps), each counter scaled by what it reads for a plain 1 GiB device copy
+# (--copy-probe): FETCH_SIZE reads half the bytes fetched, WRITE_SIZE all of
+# them.  The figures hold only for the kernel sources they were taken on: the
+# SHA-1 covers those files, and traffic is reported as null once they differ.
+# Summary and commands: profiles/contraction_hbm_traffic.md.
+KERNEL_SOURCES = ["f12_big.h", "f12_common.h", "f12_launch.h", "f12_internal.h", "f12_kernels.hip",
+                  "f12_dd.h"] + ["f12_big_lab%d.hip" % i for i in range(7)]
+TRAFFIC_RECORD = {
+    "sources_sha1": "fa8153fe1473a38b51b44251eaf089378b8d89fc",
+    "fetch_scale": 1048576 / 524299.5,
+    "write_scale": 1.0,
+    "contraction_bytes_per_launch": 7.29657e7 + 8.99791e7,
+    "aux_bytes_per_launch": 7.90213e8 + 1.41166e9,
+}
+
+
+def kernel_sources_sha1():
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1412_5070_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 # ---------------------------------------------------------------------------
@@ -110,30 +137,113 @@ def kernel_name(la, lb, lc, ld, i5):
 # ---------------------------------------------------------------------------
 # CPU oracle on a bounded sample
 # ---------------------------------------------------------------------------
-def cpu_baseline(shells, quads, budget_s=20.0, seed=7):
-    """I3 oracle rate: quartets drawn uniformly from the I3 list among those
-    with at most 4 primitive quartets, evaluated until the time budget is
-    used; each quartet's time is scaled linearly to the list's mean
-    primitive count (the oracle's cost grows about linearly with it)."""
+def _cpu_worker(job):
+    """One worker of the CPU baseline: evaluate drawn quartets with the oracle
+    until the time budget is used; returns (quartets, scaled seconds, used s)."""
+    seed, budget_s, cand, pq, pbar = job
     from oracle import integrals
-    from synth import FACTOR_SETS
+    from synth import FACTOR_SETS, config_plain
     P1 = FACTOR_SETS["P1"]
-    ks = np.array([len(s.exps) for s in shells])
-    pq = ks[quads].prod(axis=1)
-    pbar = float(pq.mean())
-    cand = np.nonzero(pq <= 4)[0]
+    _, shells = config_plain()
     rng = np.random.default_rng(seed)
     t_scaled, used, n = 0.0, 0.0, 0
     while used < budget_s or n < 3:
-        pick = int(rng.choice(cand))
-        sh = [shells[i].as_dict() for i in quads[pick]]
+        pick = int(rng.integers(len(cand)))
+        sh = [shells[i].as_dict() for i in cand[pick]]
         t0 = time.perf_counter()
         integrals.contracted(3, *sh, P1, P1)
         dt = time.perf_counter() - t0
         used += dt
         t_scaled += dt * pbar / float(pq[pick])
         n += 1
-    return n / t_scaled, used, n
+    return n, t_scaled, used
+
+
+def cpu_baseline(shells, quads, budget_s=20.0, seed=7):
+    """I3 oracle rate on the host cores: quartets drawn uniformly from the I3
+    list among those with at most 4 primitive quartets, evaluated by one
+    process per core until each has used the time budget; each quartet's time
+    is scaled linearly to the list's mean primitive count (the oracle's cost
+    grows about linearly with it).  Workers are started fresh (spawn) and
+    never touch the GPU."""
+    import multiprocessing as mp
+    ks = np.array([len(s.exps) for s in shells])
+    pq = ks[quads].prod(axis=1)
+    pbar = float(pq.mean())
+    cand = np.nonzero(pq <= 4)[0]
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(cand, size=min(4096, len(cand)), replace=False)
+    cq = [tuple(int(v) for v in quads[i]) for i in pick]
+    cp = [int(pq[i]) for i in pick]
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    cores = max(1, min(16, cores, os.cpu_count() or 1))
+    jobs = [(seed + 1000 * w, budget_s, cq, cp, pbar) for w in range(cores)]
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map_async(_cpu_worker, jobs).get(timeout=4 * budget_s + 300)
+    rate = sum(n / t for (n, t, _) in res)
+    return rate, sum(u for (_, _, u) in res), sum(n for (n, _, _) in res), cores, res[0][0] / res[0][1]
+
+
+def copy_probe(nbytes):
+    """A fill of nbytes, then three copies of nbytes between two HBM buffers."""
+    import torch
+    n = nbytes // 8
+    src = torch.empty(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty(n, dtype=torch.float64, device="cuda")
+    src.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "copies": 3, "fills": 1}))
+
+
+def stored_sample_errors(work, shells):
+    """Block errors of each class against the stored oracle values of quartets
+    sampled from the 20-atom list (tests/golden/plain20.npz, written by the
+    oracle), evaluated one quartet per launch through the same list."""
+    import torch
+    from paper_1412_5070_amd import f12int
+    path = os.path.join(ROOT, "tests", "golden", "plain20.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        gold = {k: z[k] for k in z.files}
+    res = {}
+    for wk in work:
+        cls = wk["cls"]
+        keys = wk["k128"]
+        worst, n, n_small, worst_abs_small = 0.0, 0, 0, 0.0
+        for name, ref in gold.items():
+            parts = name.split("_")
+            if parts[0] != "c%d" % cls:
+                continue
+            qd = [int(v) for v in parts[1:]]
+            hit = np.flatnonzero(keys == ((qd[0] * 128 + qd[1]) * 128 + qd[2]) * 128 + qd[3])
+            if len(hit) != 1:
+                raise RuntimeError("stored sample quartet %s not in the I%d list" % (qd, cls))
+            i = int(hit[0])
+            offs = wk["offs"]
+            out = torch.empty(int(offs[i + 1] - offs[i]), dtype=torch.float64, device="cuda")
+            f12int.eval_into(wk["Q"], wk["kern"], out, i, i + 1)
+            got = out.cpu().numpy()
+            scale = float(np.max(np.abs(ref)))
+            if cls == 5:
+                # I5 = 1/2 (lap_A - lap_B) I3 is scored on the scale of bra exponent x I3
+                ref3 = gold["c3_%d_%d_%d_%d" % tuple(qd)]
+                bexp = max(float(np.max(shells[qd[0]].exps)), float(np.max(shells[qd[1]].exps)))
+                scale = max(scale, bexp * float(np.max(np.abs(ref3))))
+            err = float(np.max(np.abs(got - ref)))
+            n += 1
+            if scale >= 1e-12:
+                worst = max(worst, err / scale)
+            else:
+                n_small += 1
+                worst_abs_small = max(worst_abs_small, err)
+        res["I%d" % cls] = {"max_block_rel_err": worst, "blocks": n, "negligible_blocks": n_small,
+                            "negligible_max_abs_err": worst_abs_small}
+    f12int.stream_status()
+    return res
 
 
 # ---------------------------------------------------------------------------
@@ -150,11 +260,17 @@ def main():
     ap.add_argument("--pipeline", action="store_true",
                     help="run the next slice's radial derivatives on a second stream while the current "
                          "slice contracts (launch timings then overlap)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (three times) and exit: "
+                         "the reference reading that scales the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the integral path has no multi-GPU mode; use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
     from paper_1412_5070_amd import f12int
@@ -197,7 +313,9 @@ def main():
         # that slice s+1's derivatives can run while slice s contracts
         Q2 = f12int.Quartets.build(pairs, pairs, cls) if args.pipeline else None
         work.append(dict(cls=cls, kern=kern, Q=Q, Q2=Q2, offs=offs, groups=groups, cprim=cprim, cbra=cbra,
-                         cap=cap, nq=len(key), quads=quads if cls == 3 else None))
+                         cap=cap, nq=len(key), quads=quads if cls == 3 else None,
+                         k128=((quads[:, 0].astype(np.int64) * 128 + quads[:, 1]) * 128 + quads[:, 2]) * 128
+                         + quads[:, 3]))
         log("I%d: %d quartets in %d groups" % (cls, len(key), len(groups)))
 
     # output rings in HBM, one per class (each class's stream writes its own)
@@ -268,9 +386,11 @@ def main():
                 if record is not None:
                     la, lb, lc, ld = lq
                     i5 = wk["cls"] == 5
-                    fl = contraction_flops(la, lb, lc, ld, i5, int(wk["cprim"][s1] - wk["cprim"][s0]),
-                                           int(wk["cbra"][s1] - wk["cbra"][s0]), s1 - s0)
-                    record["launches"].append((kernel_name(la, lb, lc, ld, i5), fl, e0, e1))
+                    npq = int(wk["cprim"][s1] - wk["cprim"][s0])
+                    fl = contraction_flops(la, lb, lc, ld, i5, npq, int(wk["cbra"][s1] - wk["cbra"][s0]), s1 - s0)
+                    # algorithmic HBM bytes: blocks written, A_0..A_L read, four list entries per quartet
+                    nbytes = 8 * size + 8 * (la + lb + lc + ld + (2 if i5 else 0) + 1) * npq + 32 * (s1 - s0)
+                    record["launches"].append((kernel_name(la, lb, lc, ld, i5), fl, e0, e1, nbytes))
             ev_cls1.record(st)
             if record is not None:
                 record["classes"].append((wk["cls"], nq, ev_cls0, ev_cls1))
@@ -303,11 +423,13 @@ def main():
     per_class_rate = {k: v[0] / v[1] for k, v in per_class.items()}
 
     by_kernel = {}
-    for (name, fl, e0, e1) in rec["launches"]:
+    alg_bytes = 0
+    for (name, fl, e0, e1, nb) in rec["launches"]:
         d = by_kernel.setdefault(name, [0, 0.0, 0.0])
         d[0] += 1
         d[1] += fl
         d[2] += e0.elapsed_time(e1) / 1e3
+        alg_bytes += nb
     dom = max(by_kernel, key=lambda k: by_kernel[k][2])
     n_c = sum(v[0] for v in by_kernel.values())
     fl_c = sum(v[1] for v in by_kernel.values())
@@ -316,17 +438,26 @@ def main():
     aux_time = sum(a.elapsed_time(b) / 1e3 for (a, b) in rec["aux"])
     gpu_time = sum(v[1] for v in per_class.values())
 
+    log("stored oracle sample")
+    accuracy = stored_sample_errors(work, shells)
+
+    rec_ok = TRAFFIC_RECORD["sources_sha1"] == kernel_sources_sha1()
+    traffic = TRAFFIC_RECORD["contraction_bytes_per_launch"] if rec_ok else None
+    aux_traffic = TRAFFIC_RECORD["aux_bytes_per_launch"] if rec_ok else None
+
     cpu = None
     if not args.no_cpu_baseline:
         wk3 = [wk for wk in work if wk["cls"] == 3]
         if wk3:
             log("CPU oracle sample")
-            rate, used, nsamp = cpu_baseline(shells, wk3[0]["quads"])
-            log("CPU oracle: %.3g quartets/s" % rate)
-            cpu = {"value": rate, "unit": "quartets/s", "cores": 1, "kind": "oracle",
+            rate, used, nsamp, cores, rate1 = cpu_baseline(shells, wk3[0]["quads"])
+            log("CPU oracle: %.3g quartets/s on %d cores" % (rate, cores))
+            cpu = {"value": rate, "unit": "quartets/s", "cores": cores, "kind": "oracle",
+                   "value_one_core": rate1,
                    "sample": "I3: %d quartets drawn uniformly from the 20-atom list among those with "
                              "<= 4 primitive quartets, each time scaled to the list's mean primitive "
-                             "count; %.1f s of CPU work on one core" % (nsamp, used)}
+                             "count; %.1f s of CPU work in %d worker processes, one per core"
+                             % (nsamp, used, cores)}
 
     line = {
         "metric": METRIC,
@@ -358,7 +489,10 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE x %.4f + WRITE_SIZE x %.4f)"
+                            % (TRAFFIC_RECORD["fetch_scale"], TRAFFIC_RECORD["write_scale"]),
+            "algorithmic_bytes_per_launch": alg_bytes / n_c,
             "launches": n_c,
             "avg_launch_ms": contraction_time / n_c * 1e3,
             "flops_per_launch": fl_c / n_c,
@@ -368,8 +502,9 @@ def main():
                 "avg_launch_ms": by_kernel[dom][2] / by_kernel[dom][0] * 1e3,
                 "achieved": by_kernel[dom][1] / by_kernel[dom][2] / 1e12},
             "aux_kernel": {"launches": len(rec["aux"]), "avg_launch_ms": aux_time / max(len(rec["aux"]), 1) * 1e3,
-                           "share_of_gpu_time": aux_time / gpu_time},
+                           "share_of_gpu_time": aux_time / gpu_time, "traffic": aux_traffic},
         },
+        "accuracy_vs_stored_oracle": accuracy,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -57,6 +57,24 @@ def test_radial_coulomb_mp_fallback():
             assert abs(A[0, n] - ref) <= 1e-20 * abs(ref)
 
 
+@pytest.mark.parametrize("cls,fac,xi,T,n", [(2, "P1", 1.0, 40.0, 14), (6, "P1", 1.0, 40.0, 14),
+                                            (4, "P4", 0.5, 60.0, 12)])
+def test_radial_mp_route_agrees_with_dd_at_handover(cls, fac, xi, T, n):
+    """radial_auto hands over from the DD quadrature to the mpmath one where the
+    split form's cancellation exceeds 13 digits (T from about 40 at n = 14).
+    Near that hand-over both quadratures must give the same A_n, on the
+    (2 xi)^n-scaled envelope, for the geminal kernels too (the mpmath route
+    is used at large T only; its panels are too coarse below T ~ 30)."""
+    F = FACTOR_SETS[fac]
+    assert radial.cancellation_digits(T, n) > 13 - 2  # at or near the hand-over
+    R = math.sqrt(T / xi)
+    a = radial.radial_derivatives(cls, [xi], [R], n, F, F).to_float().ravel()
+    b = np.array([float(v) for v in radial.radial_derivatives_mp(cls, xi, R, n, F, F)])
+    sc = (2 * xi) ** np.arange(n + 1)
+    err = np.max(np.abs(a - b) / sc) / np.max(np.abs(b) / sc)
+    assert err < 1e-13, (T, n, err)
+
+
 def _geminal_B(mu, xi, u):
     """Short-range I2 kernel (1/r + 1/2) e^{-mu r^2}, as B/(pi/(p+q))^{3/2}:
     e^{-mu r^2}/r -> 2 pi/(mu+xi) e^{-mu xi u/(mu+xi)} F_0(xi^2 u/(mu+xi)),
