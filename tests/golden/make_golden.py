@@ -16,6 +16,10 @@ Sets:
   plain20  quartets sampled from the 20-atom molecule (seed 5070), stratified
            by total angular momentum, restricted to at most 64 primitive
            quartets so that the oracle finishes; classes I2-I6, P1.
+  factors  the 3-atom s+p molecule (seed 1412) with the other factor sets:
+           P2 (non-integer rho < -1) for I2, I3, I5; P4 (integer rho >= 0)
+           for I2-I6; the mixed pair (f, f') = (P1, P4) for I4 and I6; I3
+           beside every I5 entry (the scale of its error).
 """
 import os
 import sys
@@ -89,8 +93,24 @@ def plain20_quads(n_per_L=2, max_prim=64, seed=99):
     return [q for L in sorted(by_L) for q in by_L[L]]
 
 
+# the "factors" set: (class, f, f') and the tiny molecule's quartets
+FACTOR_CASES = [(2, "P2", "P2"), (3, "P2", "P2"), (5, "P2", "P2"), (2, "P4", "P4"), (3, "P4", "P4"),
+                (4, "P4", "P4"), (5, "P4", "P4"), (6, "P4", "P4"), (4, "P1", "P4"), (6, "P1", "P4")]
+FACTOR_QUADS = [(0, 0, 0, 0), (1, 0, 2, 3), (3, 1, 4, 2), (3, 3, 5, 1)]
+
+
+def factor_key(cls, f, fp, quad):
+    return "c%d_%s_%s_%d_%d_%d_%d" % ((cls, f, fp) + tuple(quad))
+
+
 def _job(args):
-    setname, cls, quad = args
+    setname, cls, quad = args[:3]
+    if setname == "factors":
+        from synth import tiny_config
+        f, fp = args[3], args[4]
+        sh = [tiny_config()[1][i].as_dict() for i in quad]
+        return args, np.asarray(integrals.contracted(cls, *sh, FACTOR_SETS[f], FACTOR_SETS[fp]),
+                                dtype=np.float64).ravel()
     shells = {"df3": df3_shells, "deep": deep_shells}.get(setname, lambda: config_plain()[1])()
     sh = [shells[i].as_dict() for i in quad]
     return args, np.asarray(integrals.contracted(cls, *sh, P1, P1), dtype=np.float64).ravel()
@@ -103,17 +123,24 @@ def build(setname):
         jobs += [(setname, 3, q) for q in DF3_QUADS_I5 if q not in DF3_QUADS]
     elif setname == "deep":
         jobs = [(setname, c, q) for c in (5, 3, 6) for q in DEEP_QUADS]
+    elif setname == "factors":
+        cases = list(FACTOR_CASES) + [(3, f, fp) for (c, f, fp) in FACTOR_CASES if c == 5]
+        jobs = [(setname, c, q, f, fp) for (c, f, fp) in cases for q in FACTOR_QUADS]
     else:
         quads = plain20_quads()
         jobs = [(setname, c, q) for c in (5, 2, 3, 4, 6) for q in quads]
     out = {}
     with Pool(int(os.environ.get("GOLDEN_PROCS", "6"))) as pool:
-        for (sname, cls, quad), val in pool.imap_unordered(_job, jobs):
-            out["c%d_%d_%d_%d_%d" % ((cls,) + tuple(quad))] = val
-            print(sname, cls, quad, flush=True)
+        for args, val in pool.imap_unordered(_job, jobs):
+            sname, cls, quad = args[:3]
+            if sname == "factors":
+                out[factor_key(cls, args[3], args[4], quad)] = val
+            else:
+                out["c%d_%d_%d_%d_%d" % ((cls,) + tuple(quad))] = val
+            print(*args, flush=True)
     np.savez_compressed(os.path.join(HERE, setname + ".npz"), **out)
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or ["df3", "deep", "plain20"]):
+    for name in (sys.argv[1:] or ["df3", "deep", "plain20", "factors"]):
         build(name)

@@ -278,6 +278,40 @@ def test_schwarz_screening(lib, cls):
         assert np.array_equal(hs[os_[i]:os_[i + 1]], hf[of[j]:of[j + 1]]), q
 
 
+def _factor_cases():
+    import os
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import FACTOR_CASES
+    return FACTOR_CASES
+
+
+@pytest.mark.parametrize("cls,f,fp", _factor_cases())
+def test_factor_sets_vs_golden(lib, cls, f, fp):
+    """Whole blocks with the other factor sets on the 3-atom s+p molecule:
+    P2 (non-integer rho < -1, W orders below -1), P4 (integer rho >= 0) and
+    the mixed pair (P1, P4) of I4/I6, against stored oracle values."""
+    import os
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import FACTOR_QUADS, factor_key
+    golden = _golden("factors")
+    shells = _tiny()
+    basis = lib.Basis.from_shells(shells)
+    pairs = lib.Pairs(basis, 1)
+    k = lib.Kernel(cls, FACTOR_SETS[f], FACTOR_SETS[fp])
+    print(f"factors cls={cls} f={f} f'={fp} quads={FACTOR_QUADS}", flush=True)
+    got = run_quads(lib, basis, pairs, k, cls, FACTOR_QUADS)
+    for qd in FACTOR_QUADS:
+        ref = golden[factor_key(cls, f, fp, qd)]
+        if cls == 5:
+            ref3 = golden[factor_key(3, f, fp, qd)]
+            e = i5_block_err(got[qd], ref, ref3, np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps]))
+            ok = e < 1e-12
+        else:
+            ok, e, _ = block_ok(got[qd], ref)
+        print(f"  {qd} err {e:.2e}", flush=True)
+        assert ok, (qd, e)
+
+
 @pytest.mark.parametrize("cls", [3, 5, 6])
 def test_deep_contractions_vs_golden(lib, cls):
     """Deep contractions: 36 and 256 ket primitive pairs (several staging
