@@ -326,25 +326,29 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
     const double ea = bra.ea[ppb], eb = bra.eb[ppb], pb = bra.p[ppb];
     const double Pb0 = bra.Px[ppb], Pb1 = bra.Py[ppb], Pb2 = bra.Pz[ppb];
     const double cab = bra.cab[ppb];
-    if (tid < 3) {
-      if constexpr (MODE == 2) {
-        const double *E = Eb + tid * Eab1;
-        double *D = Fb + tid * Dab1;
-        e_table(ea, eb, ABb[tid], la + 2, lb + 2, Eb + tid * Eab1, nullptr);
-        for (int i = 0; i <= la; ++i)
-          for (int j = 0; j <= lb; ++j)
-            for (int t = 0; t <= i + j + 2; ++t) {
-              const double e0 = E[(i * ESb + j) * ESt + t];
-              double v = (2.0 * eb * (2 * j + 1) - 2.0 * ea * (2 * i + 1)) * e0 +
-                         4.0 * ea * ea * E[((i + 2) * ESb + j) * ESt + t] -
-                         4.0 * eb * eb * E[(i * ESb + j + 2) * ESt + t];
-              if (i >= 2) v += i * (i - 1) * E[((i - 2) * ESb + j) * ESt + t];
-              if (j >= 2) v -= j * (j - 1) * E[(i * ESb + j - 2) * ESt + t];
-              D[(i * (lb + 1) + j) * DSt + t] = 0.5 * v;
-            }
-      } else {
-        e_table(ea, eb, ABb[tid], la, lb, Eb + tid * Eab1, I5 ? Fb + tid * Eab1 : nullptr);
+    // bra tables of this primitive pair, built by the whole work-group (the
+    // previous pair's bra transform ended with a barrier)
+    if constexpr (MODE == 2) {
+      e_tables_wg(ea, eb, ABb[0], ABb[1], ABb[2], la + 2, lb + 2, Eb, nullptr, Eab1, tid, NT);
+      // D^{ij}_t of the Laplacian form, one entry per thread, t <= i + j + 2
+      const int nd1 = (la + 1) * (lb + 1) * DSt;
+      for (int k = tid; k < 3 * nd1; k += NT) {
+        const int d = k / nd1;
+        const int r = k - d * nd1;
+        const int t = r % DSt, ij = r / DSt;
+        const int i = ij / (lb + 1), j = ij - (ij / (lb + 1)) * (lb + 1);
+        if (t > i + j + 2) continue;
+        const double *E = Eb + d * Eab1;
+        const double e0 = E[(i * ESb + j) * ESt + t];
+        double v = (2.0 * eb * (2 * j + 1) - 2.0 * ea * (2 * i + 1)) * e0 +
+                   4.0 * ea * ea * E[((i + 2) * ESb + j) * ESt + t] -
+                   4.0 * eb * eb * E[(i * ESb + j + 2) * ESt + t];
+        if (i >= 2) v += i * (i - 1) * E[((i - 2) * ESb + j) * ESt + t];
+        if (j >= 2) v -= j * (j - 1) * E[(i * ESb + j - 2) * ESt + t];
+        Fb[d * Dab1 + (i * (lb + 1) + j) * DSt + t] = 0.5 * v;
       }
+    } else {
+      e_tables_wg(ea, eb, ABb[0], ABb[1], ABb[2], la, lb, Eb, I5 ? Fb : nullptr, Eab1, tid, NT);
     }
 #pragma unroll 1
     for (int comp = 0; comp < (I5 ? 4 : 1); ++comp) {

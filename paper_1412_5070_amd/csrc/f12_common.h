@@ -48,49 +48,72 @@ __host__ __device__ inline int nc2(int l) { return (l + 1) * (l + 2) / 2; }
 // Layout E[(i * (lb+1) + j) * (la+lb+1) + t].
 // ---------------------------------------------------------------------------
 
-__device__ inline void e_table(double a, double b, double AB, int la, int lb, double *E, double *Fd) {
-  const int nj = lb + 1, ntt = la + lb + 1;
 #define EI(i, j, t) (((i) * nj + (j)) * ntt + (t))
+
+// The tables of the three directions are built by a whole work-group: the
+// entries of one level N = i + j depend only on level N - 1, so each level is
+// computed in parallel over (direction, i, t), with one barrier per level.
+// Direction d is at E + d * stride (and Fd + d * stride).  Every thread of the
+// work-group must call it.
+__device__ inline void e_tables_wg(double a, double b, double ABx, double ABy, double ABz, int la,
+                                   int lb, double *E, double *Fd, int stride, int tid, int nt) {
+  const int nj = lb + 1, ntt = la + lb + 1;
   const int ne = (la + 1) * nj * ntt;
-  for (int k = 0; k < ne; ++k) {
-    E[k] = 0.0;
-    if (Fd) Fd[k] = 0.0;
+  for (int k = tid; k < 3 * ne; k += nt) {
+    const int d = k / ne, r = k - d * ne;
+    E[d * stride + r] = 0.0;
+    if (Fd) Fd[d * stride + r] = 0.0;
   }
+  __syncthreads();
   const double p = a + b;
   const double mu = a * b / p;
   const double i2p = 0.5 / p;
-  E[EI(0, 0, 0)] = exp(-mu * AB * AB);
-  if (Fd) Fd[EI(0, 0, 0)] = -2.0 * mu * AB * E[EI(0, 0, 0)];
+  if (tid < 3) {
+    const double ab = tid == 0 ? ABx : (tid == 1 ? ABy : ABz);
+    const double e0 = exp(-mu * ab * ab);
+    E[tid * stride + EI(0, 0, 0)] = e0;
+    if (Fd) Fd[tid * stride + EI(0, 0, 0)] = -2.0 * mu * ab * e0;
+  }
+  __syncthreads();
   for (int N = 1; N <= la + lb; ++N) {
-    for (int i = (N - lb > 0 ? N - lb : 0); i <= (la < N ? la : N); ++i) {
+    const int i0 = N - lb > 0 ? N - lb : 0, i1 = la < N ? la : N;
+    const int per = (i1 - i0 + 1) * (N + 1);  // (i, t) entries of one direction
+    for (int k = tid; k < 3 * per; k += nt) {
+      const int d = k / per, r = k - d * per;
+      const int i = i0 + r / (N + 1), t = r - (r / (N + 1)) * (N + 1);
       const int j = N - i;
-      for (int t = 1; t <= N; ++t) {
+      double *Ed = E + d * stride;
+      double *Fdd = Fd ? Fd + d * stride : nullptr;
+      if (t >= 1) {
         double v = 0.0, w = 0.0;
         if (i > 0) {
-          v += i * E[EI(i - 1, j, t - 1)];
-          if (Fd) w += i * Fd[EI(i - 1, j, t - 1)];
+          v += i * Ed[EI(i - 1, j, t - 1)];
+          if (Fd) w += i * Fdd[EI(i - 1, j, t - 1)];
         }
         if (j > 0) {
-          v += j * E[EI(i, j - 1, t - 1)];
-          if (Fd) w += j * Fd[EI(i, j - 1, t - 1)];
+          v += j * Ed[EI(i, j - 1, t - 1)];
+          if (Fd) w += j * Fdd[EI(i, j - 1, t - 1)];
         }
-        E[EI(i, j, t)] = v * i2p / t;
-        if (Fd) Fd[EI(i, j, t)] = w * i2p / t;
-      }
-      if (i > 0) {
-        const double c = -(b / p) * AB;
-        E[EI(i, j, 0)] = c * E[EI(i - 1, j, 0)] + E[EI(i - 1, j, 1)];
-        if (Fd)
-          Fd[EI(i, j, 0)] = c * Fd[EI(i - 1, j, 0)] + Fd[EI(i - 1, j, 1)] -
-                              (b / p) * E[EI(i - 1, j, 0)];
+        Ed[EI(i, j, t)] = v * i2p / t;
+        if (Fd) Fdd[EI(i, j, t)] = w * i2p / t;
       } else {
-        const double c = (a / p) * AB;
-        E[EI(i, j, 0)] = c * E[EI(i, j - 1, 0)] + E[EI(i, j - 1, 1)];
-        if (Fd)
-          Fd[EI(i, j, 0)] = c * Fd[EI(i, j - 1, 0)] + Fd[EI(i, j - 1, 1)] +
-                              (a / p) * E[EI(i, j - 1, 0)];
+        const double ab = d == 0 ? ABx : (d == 1 ? ABy : ABz);
+        if (i > 0) {
+          const double c = -(b / p) * ab;
+          Ed[EI(i, j, 0)] = c * Ed[EI(i - 1, j, 0)] + Ed[EI(i - 1, j, 1)];
+          if (Fd)
+            Fdd[EI(i, j, 0)] = c * Fdd[EI(i - 1, j, 0)] + Fdd[EI(i - 1, j, 1)] -
+                               (b / p) * Ed[EI(i - 1, j, 0)];
+        } else {
+          const double c = (a / p) * ab;
+          Ed[EI(i, j, 0)] = c * Ed[EI(i, j - 1, 0)] + Ed[EI(i, j - 1, 1)];
+          if (Fd)
+            Fdd[EI(i, j, 0)] = c * Fdd[EI(i, j - 1, 0)] + Fdd[EI(i, j - 1, 1)] +
+                               (a / p) * Ed[EI(i, j - 1, 0)];
+        }
       }
     }
+    __syncthreads();
   }
 }
 #undef EI
