@@ -130,9 +130,11 @@ __device__ __forceinline__ void load_col(const double *p, int last, double (&c)[
 constexpr int HC_T = LTOT_MAX + 1, HC_I = LTOT_MAX / 2 + 1;
 
 // X-direction partial sums of the closed form below, one row per T:
-//   G_T[n] = sum_i c(T,i) X^(T-2i) A_{T-i+n},  n = 0..L-T  (row stride L+1).
+//   G_T[n] = sum_i c(T,i) X^(T-2i) A_{T-i+n},  n = 0..L-T  (row stride L+1,
+// entries past L-T are 0).  One entry per call, so that a work-group spreads
+// the rows over (T, n).
 template <int L>
-__device__ __forceinline__ void g_row(int T, double X, const double *A, const double *hc, double *G) {
+__device__ __forceinline__ double g_entry(int T, int n, double X, const double *A, const double *hc) {
   constexpr int H = L / 2;
   double hx[H + 1];
   {
@@ -147,20 +149,15 @@ __device__ __forceinline__ void g_row(int T, double X, const double *A, const do
       }
     }
   }
-  const int rem = L - T;
-  double g[L + 1];
+  double g = 0.0;
+  if (n <= L - T) {
 #pragma unroll
-  for (int n = 0; n <= L; ++n) g[n] = 0.0;
-#pragma unroll
-  for (int i = 0; i <= H; ++i) {
-    if (2 * i > T) continue;
-    const double *Ap = A + (T - i);
-#pragma unroll
-    for (int n = 0; n <= L; ++n)
-      if (n <= rem) g[n] = fma(hx[i], Ap[n], g[n]);
+    for (int i = 0; i <= H; ++i) {
+      if (2 * i > T) continue;
+      g = fma(hx[i], A[T - i + n], g);
+    }
   }
-#pragma unroll
-  for (int n = 0; n <= L; ++n) G[n] = g[n];
+  return g;
 }
 
 // One Hermite line R_{T,U,w+SH}, w = 0..NW-1, of the primitive quartet, from
@@ -360,8 +357,10 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
       for (int kc0 = 0; kc0 < nket; kc0 += S::KC) {
       const int nkc = nket - kc0 < S::KC ? nket - kc0 : S::KC;
       // stage the chunk's ket primitive data and radial derivatives (one
-      // round of global loads instead of one per R level)
-      for (int w = tid; w < nkc; w += NT) {
+      // round of global loads instead of one per R level); the ket data does
+      // not depend on the bra primitive, so a single chunk is staged once
+      const bool stage_kd = nket > S::KC || (ib == 0 && comp == 0);
+      for (int w = tid; stage_kd && w < nkc; w += NT) {
         const int64_t ppk = ket.pp_off[kp] + kc0 + w;
         const double qk = ket.p[ppk], ed = ket.eb[ppk];
         KD[w * S::KDW + 0] = ket.Px[ppk];
@@ -403,11 +402,14 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
         // (T', U', sh) = (T, U, 0), the shifted line of an I5 component, or
         // the three terms of R_lap.
         const int nvj = nkc - jk0 < NJ ? nkc - jk0 : NJ;  // ket primitives in this pass
-        for (int k = tid; k < nvj * (L + 1); k += NT) {
-          const int jj = k / (L + 1), T = k - jj * (L + 1);
+        // rows G_T[n] of the NJ ket primitives, one entry (jj, T, n) per thread
+        for (int k = tid; k < nvj * (L + 1) * (L + 1); k += NT) {
+          const int jj = k / ((L + 1) * (L + 1));
+          const int r = k - jj * ((L + 1) * (L + 1));
+          const int T = r / (L + 1), n = r - (r / (L + 1)) * (L + 1);
           const int jk = jk0 + jj;
-          g_row<L>(T, KD[jk * S::KDW + 0] - Pb0, AS + jk * (L + 1), hc,
-                   lds + S::oRp + jj * S::PJ + S::jG + T * (L + 1));
+          lds[S::oRp + jj * S::PJ + S::jG + T * (L + 1) + n] =
+              g_entry<L>(T, n, KD[jk * S::KDW + 0] - Pb0, AS + jk * (L + 1), hc);
         }
         __syncthreads();
         for (int k = tid; k < nvj * S::NLP; k += NT) {
