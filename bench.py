@@ -46,11 +46,11 @@ METRIC = "contracted shell-quartets/s per F12 class at ≤1e-12 rel err; % FP64 
 KERNEL_SOURCES = ["f12_big.h", "f12_common.h", "f12_launch.h", "f12_internal.h", "f12_kernels.hip",
                   "f12_dd.h"] + ["f12_big_lab%d.hip" % i for i in range(7)]
 TRAFFIC_RECORD = {
-    "sources_sha1": "fa8153fe1473a38b51b44251eaf089378b8d89fc",
+    "sources_sha1": "183de71112dda9266b304ba97523db05c17c175d",
     "fetch_scale": 1048576 / 524299.5,
     "write_scale": 1.0,
-    "contraction_bytes_per_launch": 7.29657e7 + 8.99791e7,
-    "aux_bytes_per_launch": 7.90213e8 + 1.41166e9,
+    "contraction_bytes_per_launch": 7.35116e7 + 8.50433e7,
+    "aux_bytes_per_launch": 7.90327e8 + 1.41163e9,
 }
 
 
