@@ -51,6 +51,11 @@ TRAFFIC_RECORD = {
     "write_scale": 1.0,
     "contraction_bytes_per_launch": 7.35116e7 + 8.50433e7,
     "aux_bytes_per_launch": 7.90327e8 + 1.41163e9,
+    # FP64 flops issued per launch, 64 lanes x (2 SQ_INSTS_VALU_FMA_F64 + SQ_INSTS_VALU_MUL_F64 +
+    # SQ_INSTS_VALU_ADD_F64), from one more --pmc pass (profiles/contraction_fp64_counters.md);
+    # an upper bound, since lanes masked off are counted too
+    "contraction_hw_fp64_flops_per_launch": 3.420e10,
+    "aux_hw_fp64_flops_per_launch": 1.128e10,
 }
 
 
@@ -493,6 +498,11 @@ def main():
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE x %.4f + WRITE_SIZE x %.4f)"
                             % (TRAFFIC_RECORD["fetch_scale"], TRAFFIC_RECORD["write_scale"]),
             "algorithmic_bytes_per_launch": alg_bytes / n_c,
+            "hardware_fp64": None if not rec_ok else {
+                "flops_per_launch": TRAFFIC_RECORD["contraction_hw_fp64_flops_per_launch"],
+                "achieved": TRAFFIC_RECORD["contraction_hw_fp64_flops_per_launch"] / (contraction_time / n_c) / 1e12,
+                "frac": TRAFFIC_RECORD["contraction_hw_fp64_flops_per_launch"] / (contraction_time / n_c) / 1e12
+                        / FP64_VECTOR_PEAK_TFLOPS},
             "launches": n_c,
             "avg_launch_ms": contraction_time / n_c * 1e3,
             "flops_per_launch": fl_c / n_c,
@@ -502,7 +512,9 @@ def main():
                 "avg_launch_ms": by_kernel[dom][2] / by_kernel[dom][0] * 1e3,
                 "achieved": by_kernel[dom][1] / by_kernel[dom][2] / 1e12},
             "aux_kernel": {"launches": len(rec["aux"]), "avg_launch_ms": aux_time / max(len(rec["aux"]), 1) * 1e3,
-                           "share_of_gpu_time": aux_time / gpu_time, "traffic": aux_traffic},
+                           "share_of_gpu_time": aux_time / gpu_time, "traffic": aux_traffic,
+                           "hardware_fp64_achieved": None if not rec_ok else
+                           TRAFFIC_RECORD["aux_hw_fp64_flops_per_launch"] / (aux_time / max(len(rec["aux"]), 1)) / 1e12},
         },
         "accuracy_vs_stored_oracle": accuracy,
         "cpu_baseline": cpu,
