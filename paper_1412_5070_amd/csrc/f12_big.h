@@ -544,6 +544,26 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
       }
       __syncthreads();
       const double cw = cab * (I5 ? (comp == 0 ? (ea - eb) / (2.0 * pb) : -1.0) : 1.0);
+      // sum over t <= nx, u <= ny, v <= nz of (-1)^(t+u+v) ex[t] ey[u] ez[v] V[t,u,v][f]; the
+      // signed z coefficients are held in registers over the shape's whole v range
+      auto box = [&](const double *exr, const double *eyr, const double *ezr, int nx, int ny, int nz,
+                     int f) {
+        double ez[LAB + 1];
+#pragma unroll
+        for (int v = 0; v <= LAB; ++v) ez[v] = v <= nz ? ((v & 1) ? -ezr[v] : ezr[v]) : 0.0;
+        double sb = 0.0;
+        for (int t = 0; t <= nx; ++t)
+          for (int u = 0; u <= ny; ++u) {
+            const double exy = ((t + u) & 1) ? -exr[t] * eyr[u] : exr[t] * eyr[u];
+            const double *vr = Vs + vline(t, u) * S::NF0 + f;
+            double sv = 0.0;
+#pragma unroll
+            for (int v = 0; v <= LAB; ++v)
+              if (v <= nz) sv = fma(ez[v], vr[v * S::NF0], sv);
+            sb = fma(exy, sv, sb);
+          }
+        return sb;
+      };
 #pragma unroll
       for (int k = 0; k < S::MAXU; ++k) {
         const int e = tid + NT * k;
@@ -564,33 +584,13 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
               const double *ezr = d == 2 ? dr[2] : er[2];
               const int nx = ax + bx + (d == 0 ? 2 : 0), ny = ay + by + (d == 1 ? 2 : 0),
                         nz = az + bz + (d == 2 ? 2 : 0);
-              for (int t = 0; t <= nx; ++t)
-                for (int u = 0; u <= ny; ++u) {
-                  const double exy = ((t + u) & 1) ? -exr[t] * eyr[u] : exr[t] * eyr[u];
-                  const double *vr = Vs + vline(t, u) * S::NF0 + f;
-                  double sv = 0.0;
-                  for (int v = 0; v <= nz; ++v) {
-                    const double term = ezr[v] * vr[v * S::NF0];
-                    sv += (v & 1) ? -term : term;
-                  }
-                  sacc = fma(exy, sv, sacc);
-                }
+              sacc += box(exr, eyr, ezr, nx, ny, nz, f);
             }
           } else {
             const double *exr = (comp == 1 ? Fb : Eb) + (ax * (lb + 1) + bx) * (LAB + 1);
             const double *eyr = (comp == 2 ? Fb : Eb) + Eab1 + (ay * (lb + 1) + by) * (LAB + 1);
             const double *ezr = (comp == 3 ? Fb : Eb) + 2 * Eab1 + (az * (lb + 1) + bz) * (LAB + 1);
-            for (int t = 0; t <= ax + bx; ++t)
-              for (int u = 0; u <= ay + by; ++u) {
-                const double exy = ((t + u) & 1) ? -exr[t] * eyr[u] : exr[t] * eyr[u];
-                const double *vr = Vs + vline(t, u) * S::NF0 + f;
-                double sv = 0.0;
-                for (int v = 0; v <= az + bz; ++v) {
-                  const double term = ezr[v] * vr[v * S::NF0];
-                  sv += (v & 1) ? -term : term;
-                }
-                sacc = fma(exy, sv, sacc);
-              }
+            sacc = box(exr, eyr, ezr, ax + bx, ay + by, az + bz, f);
           }
           uacc[k] = fma(cw, sacc, uacc[k]);
         }
