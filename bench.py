@@ -46,11 +46,11 @@ METRIC = "contracted shell-quartets/s per F12 class at ≤1e-12 rel err; % FP64 
 KERNEL_SOURCES = ["f12_big.h", "f12_common.h", "f12_launch.h", "f12_internal.h", "f12_kernels.hip",
                   "f12_dd.h"] + ["f12_big_lab%d.hip" % i for i in range(7)]
 TRAFFIC_RECORD = {
-    "sources_sha1": "183de71112dda9266b304ba97523db05c17c175d",
+    "sources_sha1": "a6c995696cfa5fca2d19a3ddde8d9896b03b78eb",
     "fetch_scale": 1048576 / 524299.5,
     "write_scale": 1.0,
-    "contraction_bytes_per_launch": 7.35116e7 + 8.50433e7,
-    "aux_bytes_per_launch": 7.90327e8 + 1.41163e9,
+    "contraction_bytes_per_launch": 7.12356e7 + 8.73574e7,
+    "aux_bytes_per_launch": 7.90192e8 + 1.41157e9,
     # FP64 flops issued per launch, 64 lanes x (2 SQ_INSTS_VALU_FMA_F64 + SQ_INSTS_VALU_MUL_F64 +
     # SQ_INSTS_VALU_ADD_F64), from one more --pmc pass (profiles/contraction_fp64_counters.md);
     # an upper bound, since lanes masked off are counted too
