@@ -157,6 +157,24 @@ void f12_quartets_destroy(f12_quartets *q);
 int f12_eval(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
              double *d_out, int64_t out_capacity, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as f12_eval, with the same arguments and output, but the radial-
+ * derivative scratch is a fixed device array inside the library instead of
+ * the list's own buffer.  It holds the radial derivatives A_0..A_14 of
+ * F12_NOALLOC_SCRATCH_PRIMS primitive quartets (15 doubles each, 31.5 MiB),
+ * one copy per GPU kept until the process ends; ranges with more primitive quartets run in
+ * chunks that fit it.  The call performs no hipMalloc/hipFree; its first call
+ * on a device looks the array's address up once.  Errors: as f12_eval, plus
+ * F12_EBUFSIZE if one quartet of the list has more primitive quartets than
+ * the array holds.  Every call on a GPU shares that GPU's array and it keeps
+ * the previous call's contents (every value read is written first by the same
+ * call), so calls that overlap in time on one GPU (two streams, two threads)
+ * race: serialise them. */
+#define F12_NOALLOC_SCRATCH_PRIMS 262144
+int f12_eval_noalloc(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
+                     double *d_out, int64_t out_capacity, void *stream);
+
 /* The two launches of f12_eval, separately, for timing them one by one.
  * [q_begin, q_end) must lie inside one (l_a, l_b, l_c, l_d) group of the
  * public order and hold at most f12_quartets_scratch_prims primitive

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "../../include/f12int.h"
@@ -131,6 +132,7 @@ struct f12_quartets {
   DevBuf<int64_t> d_qb, d_qk, d_qoff, d_qprim;
   DevBuf<double> d_A;
   int64_t a_cap_prims = 0;
+  int64_t max_qprim = 0;  // largest primitive-quartet count of one quartet
   // range whose radial derivatives sit in d_A after f12_eval_stage(stage 1)
   int64_t stage_qa = -1, stage_qe = -1;
   const f12_kernel *stage_k = nullptr;
@@ -806,6 +808,8 @@ int finish_quartets(f12_quartets *Q, std::vector<int64_t> &qb, std::vector<int64
     Q->qprim[i + 1] =
         Q->qprim[i] + (int64_t)B->ka[b] * B->kb[b] * (int64_t)K->ka[k] * K->kb[k];
   }
+  Q->max_qprim = 0;
+  for (int64_t i = 0; i < nq; ++i) Q->max_qprim = std::max(Q->max_qprim, Q->qprim[i + 1] - Q->qprim[i]);
   Q->nq = nq;
   Q->nout = Q->qoff[nq];
   Q->nprim = Q->qprim[nq];
@@ -817,8 +821,10 @@ int finish_quartets(f12_quartets *Q, std::vector<int64_t> &qb, std::vector<int64
   return F12_OK;
 }
 
+// Evaluates [q_begin, q_end) with radial-derivative scratch A of cap_prims
+// primitive quartets (times LTOT_MAX + 1 doubles), in chunks that fit it.
 int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_end, double *d_out,
-               hipStream_t st);
+               double *A, int64_t cap_prims, hipStream_t st);
 
 }  // namespace
 
@@ -874,7 +880,7 @@ extern "C" int f12_quartets_build(const f12_pairs *bra, const f12_pairs *ket, in
       if (s) return s;
       DevBuf<double> dout;
       if (!dout.alloc(D->nout)) return F12_ENOMEM;
-      s = eval_range(D.get(), screen_kernel, 0, D->nq, dout.ptr, st);
+      s = eval_range(D.get(), screen_kernel, 0, D->nq, dout.ptr, D->d_A.ptr, D->a_cap_prims, st);
       if (s) return s;
       std::vector<double> h(D->nout);
       if (hipMemcpyAsync(h.data(), dout.ptr, D->nout * sizeof(double), hipMemcpyDeviceToHost,
@@ -950,7 +956,7 @@ extern "C" void f12_quartets_destroy(f12_quartets *q) { delete q; }
 namespace {
 
 int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_end, double *d_out,
-               hipStream_t st) {
+               double *A, int64_t cap_prims, hipStream_t st) {
   const PairsDev bra = Q->bra->dev(), ket = Q->ket->dev();
   const int i5 = (Q->cls == 5);
   const int64_t out_base = Q->qoff[q_begin];
@@ -960,18 +966,18 @@ int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_
     const int L = b.la + b.lb + b.lc + b.ld + (i5 ? 2 : 0);
     int64_t qa = lo;
     while (qa < hi) {
-      // largest chunk [qa, qe) with at most a_cap_prims primitive quartets
-      int64_t limit = Q->qprim[qa] + Q->a_cap_prims;
+      // largest chunk [qa, qe) with at most cap_prims primitive quartets
+      int64_t limit = Q->qprim[qa] + cap_prims;
       int64_t qe = std::upper_bound(Q->qprim.begin() + qa + 1, Q->qprim.begin() + hi + 1, limit) -
                    Q->qprim.begin() - 1;
       if (qe <= qa) qe = qa + 1;
       const int64_t p0 = Q->qprim[qa];
       const int64_t np = Q->qprim[qe] - p0;
       if (launch_aux(k->d_desc.ptr, bra, ket, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qprim.ptr, qa,
-                     qe - qa, p0, np, L, Q->d_A.ptr, st) != 0)
+                     qe - qa, p0, np, L, A, st) != 0)
         return F12_EDEVICE;
       if (launch_contract(bra, ket, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qoff.ptr, Q->d_qprim.ptr, qa,
-                          qe - qa, p0, np, Q->d_A.ptr, b.la, b.lb, b.lc, b.ld, i5, d_out, out_base,
+                          qe - qa, p0, np, A, b.la, b.lb, b.lc, b.ld, i5, d_out, out_base,
                           st) != 0)
         return F12_EDEVICE;
       qa = qe;
@@ -989,7 +995,7 @@ extern "C" int f12_eval(f12_quartets *q, const f12_kernel *k, int64_t q_begin, i
   if (q->qoff[q_end] - q->qoff[q_begin] > out_capacity) return F12_EBUFSIZE;
   if (q_begin == q_end) return F12_OK;
   q->stage_qa = q->stage_qe = -1;
-  return eval_range(q, k, q_begin, q_end, d_out, (hipStream_t)stream);
+  return eval_range(q, k, q_begin, q_end, d_out, q->d_A.ptr, q->a_cap_prims, (hipStream_t)stream);
 }
 
 extern "C" int f12_eval_stage(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
@@ -1030,4 +1036,50 @@ extern "C" int f12_quartets_scratch_prims(const f12_quartets *q, int64_t *n) {
   if (!q || !n) return F12_EINVAL;
   *n = q->a_cap_prims;
   return F12_OK;
+}
+
+// ============================================================================
+// evaluation without allocation
+// ============================================================================
+// Radial-derivative scratch for f12_eval_noalloc: a fixed device array, one
+// copy per GPU, kept until the process ends.  Host code never passes its name
+// to a kernel (in host code the name is only a stand-in); it passes the device
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[(size_t)F12_NOALLOC_SCRATCH_PRIMS * (LTOT_MAX + 1)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(double **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return F12_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return F12_EDEVICE;
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return F12_OK;
+}
+}  // namespace
+
+extern "C" int f12_eval_noalloc(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
+                                double *d_out, int64_t out_capacity, void *stream) {
+  if (!q || !k || !d_out || q_begin < 0 || q_end > q->nq || q_begin > q_end) return F12_EINVAL;
+  if (k->cls != q->cls) return F12_EINVAL;
+  if (q->qoff[q_end] - q->qoff[q_begin] > out_capacity) return F12_EBUFSIZE;
+  if (q_begin == q_end) return F12_OK;
+  // every chunk holds at least one whole quartet: reject a quartet whose
+  // primitive quartets exceed the fixed scratch
+  if (q->max_qprim > (int64_t)F12_NOALLOC_SCRATCH_PRIMS) return F12_EBUFSIZE;
+  double *A = nullptr;
+  int s = scratch_address(&A);
+  if (s) return s;
+  q->stage_qa = q->stage_qe = -1;
+  return eval_range(q, k, q_begin, q_end, d_out, A, (int64_t)F12_NOALLOC_SCRATCH_PRIMS,
+                    (hipStream_t)stream);
 }
