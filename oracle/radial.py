@@ -307,7 +307,15 @@ def radial_derivatives_mp(cls, xi, R, nmax, fac, facp, extra_digits=None):
         prec = mp.mp.prec
         degree = 6 if dig < 40 else 7
         gnodes = gl.get_nodes(-1, 1, degree, prec)
-        tnodes = ts.get_nodes(-1, 1, degree + 1, prec)
+        # mpmath keeps each tanh-sinh level's new abscissas apart (level k
+        # adds the odd multiples of 2^-k); the full rule of step h = 2^-D is
+        # their union with every weight times h
+        tlev = degree + 1
+        tnodes = []
+        for k in range(1, tlev + 1):
+            tnodes += ts.get_nodes(-1, 1, k, prec)
+        hstep = mp.mpf(2) ** (-tlev)
+        tnodes = [(x, w * hstep) for (x, w) in tnodes]
         pts = [(mp.mpf(0), a1, tnodes), (a1, lo, gnodes)]
         edges = [lo + (hi - lo) * k / N_PANELS for k in range(N_PANELS + 1)]
         pts += [(edges[k], edges[k + 1], gnodes) for k in range(N_PANELS)]
