@@ -134,6 +134,72 @@ def contraction_flops(la, lb, lc, ld, i5, n_prim, n_bra_prim, n_quartets):
     return per_prim * n_prim + per_bra * n_bra_prim + 2 * _hrr_fmas(la, lb, lc, ld) * n_quartets
 
 
+def e_nonzero_fraction(la, lb):
+    """Fraction of the dense bra tile E^ab_{tuv} (n_a n_b x H(l_a + l_b)) that is
+    nonzero: component pair (a, b) reaches t <= a_x + b_x, u <= a_y + b_y,
+    v <= a_z + b_z."""
+    nz = 0
+    for (ax, ay, az) in _carts(la):
+        for (bx, by, bz) in _carts(lb):
+            nz += (ax + bx + 1) * (ay + by + 1) * (az + bz + 1)
+    return nz / (_nc(la) * _nc(lb) * _hs3(la + lb))
+
+
+def method_flops(la, lb, lc, ld, i5, n_prim, n_bra_prim):
+    """Algorithmic FP64 flops of one contraction launch by the method's own
+    per-unit count (what the E.R.E route must compute, not the dense 6-D work
+    it avoids):
+      per primitive quartet: 3 C(L+4, 4) for the Hermite integrals R_tuv of
+        every order n (L = l_a+l_b+l_c+l_d, +2 for I5), plus the ket transform
+        2 H(L_ab) H(L_cd) n_c n_d (H(L) = (L+1)(L+2)(L+3)/6 Hermite functions);
+      per bra primitive pair (after the ket primitives are summed): the bra
+        transform 2 n_a n_b H(L_ab) n_c n_d times the nonzero fraction of E^ab;
+      I5: four components (the Laplacian shift and three gradients), so 4x the
+        ket and bra terms, with R at L + 2 (Eq. (I5byI3_))."""
+    Lab, Lcd = la + lb, lc + ld
+    L = Lab + Lcd + (2 if i5 else 0)
+    ncomp = 4 if i5 else 1
+    ncd = _nc(lc) * _nc(ld)
+    per_prim = 3 * math.comb(L + 4, 4) + ncomp * 2 * _hs3(Lab) * _hs3(Lcd) * ncd
+    per_bra = ncomp * 2 * _nc(la) * _nc(lb) * _hs3(Lab) * ncd * e_nonzero_fraction(la, lb)
+    return per_prim * n_prim + per_bra * n_bra_prim
+
+
+def kernel_chains(terms):
+    """Chains of the kernel's term table (equal b, g and alpha mod 1): their
+    count and, per chain, the span of integer power offsets."""
+    ch = {}
+    for (c, alpha, b, g) in terms:
+        a0 = alpha - math.floor(alpha + 1e-9)
+        if a0 < 1e-9 or a0 > 1 - 1e-9:
+            a0 = 0.0
+        key = (round(b, 9), round(g, 9), round(a0, 9))
+        m = int(round(alpha - a0))
+        lo, hi = ch.get(key, (m, m))
+        ch[key] = (min(lo, m), max(hi, m))
+    return [hi - lo for (lo, hi) in ch.values()]
+
+
+# flops of the start of one auxiliary-function ladder: one table row read and
+# its Taylor shift (16 terms, 2 flops each), plus the exponential and the
+# power of gamma that scale it
+AUX_START_FLOPS = 2 * 16 + 20 + 20
+
+
+def aux_flops(L, spans, n_prim):
+    """Algorithmic FP64 flops of the auxiliary functions and radial derivatives
+    A_0..A_L of n_prim primitive quartets:
+      per chain and per sign (+, -): a ladder start and (L + span) steps of
+        about 6 flops;
+      per sign: the recursion to the radial derivatives, about
+        2 x 4 flops x (L+1)(L+2)(2L+3)/6 entries."""
+    per = 0
+    for span in spans:
+        per += 2 * (AUX_START_FLOPS + 6 * (L + span))
+    per += 2 * 2 * 4 * (L + 1) * (L + 2) * (2 * L + 3) // 6
+    return per * n_prim
+
+
 def kernel_name(la, lb, lc, ld, i5):
     """The big_kernel instantiation family of a shell-quartet shape."""
     return "big_kernel, l_a+l_b=%d, l_c+l_d=%d%s" % (la + lb, lc + ld, ", I5" if i5 else "")
@@ -142,51 +208,74 @@ def kernel_name(la, lb, lc, ld, i5):
 # ---------------------------------------------------------------------------
 # CPU oracle on a bounded sample
 # ---------------------------------------------------------------------------
+CPU_BINS = ((1, 4), (5, 16), (17, 64))
+
+
 def _cpu_worker(job):
-    """One worker of the CPU baseline: evaluate drawn quartets with the oracle
-    until the time budget is used; returns (quartets, scaled seconds, used s)."""
-    seed, budget_s, cand, pq, pbar = job
+    """One worker of the CPU baseline: evaluate quartets of one stratum (class,
+    primitive-count bin) drawn uniformly from it with the oracle until the
+    time budget is used (at least one); returns (stratum, quartets, seconds)."""
+    stratum, seed, budget_s, cand = job
+    cls = stratum[0]
     from oracle import integrals
     from synth import FACTOR_SETS, config_plain
     P1 = FACTOR_SETS["P1"]
     _, shells = config_plain()
     rng = np.random.default_rng(seed)
-    t_scaled, used, n = 0.0, 0.0, 0
-    while used < budget_s or n < 3:
-        pick = int(rng.integers(len(cand)))
-        sh = [shells[i].as_dict() for i in cand[pick]]
+    used, n = 0.0, 0
+    while used < budget_s or n < 1:
+        q = cand[int(rng.integers(len(cand)))]
+        sh = [shells[i].as_dict() for i in q]
         t0 = time.perf_counter()
-        integrals.contracted(3, *sh, P1, P1)
-        dt = time.perf_counter() - t0
-        used += dt
-        t_scaled += dt * pbar / float(pq[pick])
+        integrals.contracted(cls, *sh, P1, P1)
+        used += time.perf_counter() - t0
         n += 1
-    return n, t_scaled, used
+    return stratum, n, used
 
 
-def cpu_baseline(shells, quads, budget_s=20.0, seed=7):
-    """I3 oracle rate on the host cores: quartets drawn uniformly from the I3
-    list among those with at most 4 primitive quartets, evaluated by one
-    process per core until each has used the time budget; each quartet's time
-    is scaled linearly to the list's mean primitive count (the oracle's cost
-    grows about linearly with it).  Workers are started fresh (spawn) and
-    never touch the GPU."""
+def cpu_baseline(work, ks, budget_s=20.0, seed=7):
+    """Oracle rate on the host cores over a stratified sample of the workload:
+    strata are (class, primitive-count bin) with bins of 1-4, 5-16 and 17-64
+    primitive quartets; one worker process per core takes one stratum (strata
+    dealt round-robin), draws quartets uniformly from it and times the oracle
+    on each until its budget is used.  The mean time per quartet of the
+    covered part of the workload is the stratum means weighted by the
+    workload's quartet counts, t = sum_s w_s t_s / sum_s w_s, and the rate on
+    C cores is C / t.  Quartets with more than 64 primitive quartets (minutes
+    each in the oracle) are not sampled: the reported coverage is the share
+    of the workload's quartets the strata hold.  Workers are started fresh
+    (spawn) and never touch the GPU."""
     import multiprocessing as mp
-    ks = np.array([len(s.exps) for s in shells])
-    pq = ks[quads].prod(axis=1)
-    pbar = float(pq.mean())
-    cand = np.nonzero(pq <= 4)[0]
-    rng = np.random.default_rng(seed)
-    pick = rng.choice(cand, size=min(4096, len(cand)), replace=False)
-    cq = [tuple(int(v) for v in quads[i]) for i in pick]
-    cp = [int(pq[i]) for i in pick]
+    strata, total = [], 0
+    for wk in work:
+        quads = wk["quads_all"]
+        pq = ks[quads].prod(axis=1)
+        total += len(quads)
+        for (lo, hi) in CPU_BINS:
+            idx = np.nonzero((pq >= lo) & (pq <= hi))[0]
+            if len(idx) == 0:
+                continue
+            rng = np.random.default_rng(seed + wk["cls"] * 10 + lo)
+            pick = rng.choice(idx, size=min(512, len(idx)), replace=False)
+            strata.append(((wk["cls"], lo, hi), len(idx), [tuple(int(v) for v in quads[i]) for i in pick]))
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     cores = max(1, min(16, cores, os.cpu_count() or 1))
-    jobs = [(seed + 1000 * w, budget_s, cq, cp, pbar) for w in range(cores)]
+    jobs = [(strata[w % len(strata)][0], seed + 1000 * w, budget_s, strata[w % len(strata)][2])
+            for w in range(max(cores, len(strata)))]
     with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map_async(_cpu_worker, jobs).get(timeout=4 * budget_s + 300)
-    rate = sum(n / t for (n, t, _) in res)
-    return rate, sum(u for (_, _, u) in res), sum(n for (n, _, _) in res), cores, res[0][0] / res[0][1]
+        res = pool.map_async(_cpu_worker, jobs).get(timeout=20 * budget_s + 600)
+    acc = {}
+    for (st, n, used) in res:
+        a = acc.setdefault(st, [0, 0.0])
+        a[0] += n
+        a[1] += used
+    wsum = sum(w for (st, w, _) in strata)
+    tbar = sum(w * acc[st][1] / acc[st][0] for (st, w, _) in strata) / wsum
+    per = {"I%d %d-%d" % st: {"quartets_timed": acc[st][0], "s_per_quartet": acc[st][1] / acc[st][0],
+                              "workload_quartets": w} for (st, w, _) in strata}
+    return {"rate": cores / tbar, "rate_one_core": 1.0 / tbar, "cores": cores, "coverage": wsum / total,
+            "quartets_timed": sum(a[0] for a in acc.values()), "cpu_seconds": sum(a[1] for a in acc.values()),
+            "strata": per}
 
 
 def copy_probe(nbytes):
@@ -206,7 +295,10 @@ def copy_probe(nbytes):
 def stored_sample_errors(work, shells):
     """Block errors of each class against the stored oracle values of quartets
     sampled from the 20-atom list (tests/golden/plain20.npz, written by the
-    oracle), evaluated one quartet per launch through the same list."""
+    oracle), evaluated one quartet per launch through the same list.  Every
+    block is scored block-relative, max |I_gpu - I_ref| / max |I_ref|; an I5
+    block that vanishes identically (a bra made of one s or p shell taken
+    twice) is scored against the largest bra exponent times max |I3|."""
     import torch
     from paper_1412_5070_amd import f12int
     path = os.path.join(ROOT, "tests", "golden", "plain20.npz")
@@ -218,35 +310,41 @@ def stored_sample_errors(work, shells):
     for wk in work:
         cls = wk["cls"]
         keys = wk["k128"]
-        worst, n, n_small, worst_abs_small = 0.0, 0, 0, 0.0
+        worst, worst_big, n, n_small, wq = 0.0, 0.0, 0, 0, None
+        n_drop, drop_max = 0, 0.0
         for name, ref in gold.items():
             parts = name.split("_")
             if parts[0] != "c%d" % cls:
                 continue
             qd = [int(v) for v in parts[1:]]
             hit = np.flatnonzero(keys == ((qd[0] * 128 + qd[1]) * 128 + qd[2]) * 128 + qd[3])
-            if len(hit) != 1:
-                raise RuntimeError("stored sample quartet %s not in the I%d list" % (qd, cls))
+            if len(hit) == 0:
+                # dropped by the screen: it must be below the threshold
+                n_drop += 1
+                drop_max = max(drop_max, float(np.max(np.abs(ref))))
+                continue
             i = int(hit[0])
             offs = wk["offs"]
             out = torch.empty(int(offs[i + 1] - offs[i]), dtype=torch.float64, device="cuda")
             f12int.eval_into(wk["Q"], wk["kern"], out, i, i + 1)
             got = out.cpu().numpy()
-            scale = float(np.max(np.abs(ref)))
-            if cls == 5:
-                # I5 = 1/2 (lap_A - lap_B) I3 is scored on the scale of bra exponent x I3
+            mx = float(np.max(np.abs(ref)))
+            scale = mx
+            if cls == 5 and qd[0] == qd[1] and shells[qd[0]].l <= 1:
                 ref3 = gold["c3_%d_%d_%d_%d" % tuple(qd)]
-                bexp = max(float(np.max(shells[qd[0]].exps)), float(np.max(shells[qd[1]].exps)))
-                scale = max(scale, bexp * float(np.max(np.abs(ref3))))
-            err = float(np.max(np.abs(got - ref)))
+                scale = float(np.max(shells[qd[0]].exps)) * float(np.max(np.abs(ref3)))
+            err = float(np.max(np.abs(got - ref))) / scale
             n += 1
-            if scale >= 1e-12:
-                worst = max(worst, err / scale)
+            if err > worst:
+                worst, wq = err, {"quartet": qd, "max_abs_integral": mx}
+            if mx >= 1e-12:
+                worst_big = max(worst_big, err)
             else:
                 n_small += 1
-                worst_abs_small = max(worst_abs_small, err)
-        res["I%d" % cls] = {"max_block_rel_err": worst, "blocks": n, "negligible_blocks": n_small,
-                            "negligible_max_abs_err": worst_abs_small}
+        res["I%d" % cls] = {"max_block_rel_err": worst, "worst_block": wq, "blocks": n,
+                            "blocks_below_1e-12": n_small, "max_block_rel_err_blocks_above_1e-12": worst_big,
+                            "sampled_blocks_dropped_by_screen": n_drop,
+                            "largest_dropped_block": drop_max}
     f12int.stream_status()
     return res
 
@@ -260,6 +358,8 @@ def main():
     ap.add_argument("--batches", type=int, default=16)
     ap.add_argument("--classes", default=",".join(str(c) for c in CLASSES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--screen-tol", type=float, default=1e-12,
+                    help="quartet screening threshold of the workload (0: every unique quartet)")
     ap.add_argument("--concurrent", action="store_true",
                     help="one stream per class, classes run concurrently (per-class rates then overlap)")
     ap.add_argument("--pipeline", action="store_true",
@@ -299,7 +399,10 @@ def main():
     work = []
     for cls in classes:
         kern = f12int.Kernel(cls, P1, P1)
-        Q = f12int.Quartets.build(pairs, pairs, cls)
+        kscr = None
+        if args.screen_tol > 0:
+            kscr = f12int.Kernel(3, P1, P1) if cls == 5 else kern
+        Q = f12int.Quartets.build(pairs, pairs, cls, screen_tol=args.screen_tol, screen_kernel=kscr)
         quads = Q.quads()
         offs = Q.offsets()
         key = ((ls[quads[:, 0]] * 4 + ls[quads[:, 1]]) * 4 + ls[quads[:, 2]]) * 4 + ls[quads[:, 3]]
@@ -316,9 +419,11 @@ def main():
             groups.append((a, b, (la, lb, lc, ld)))
         # a second copy of the list owns a second radial-derivative scratch, so
         # that slice s+1's derivatives can run while slice s contracts
-        Q2 = f12int.Quartets.build(pairs, pairs, cls) if args.pipeline else None
+        Q2 = (f12int.Quartets.build(pairs, pairs, cls, screen_tol=args.screen_tol, screen_kernel=kscr)
+              if args.pipeline else None)
         work.append(dict(cls=cls, kern=kern, Q=Q, Q2=Q2, offs=offs, groups=groups, cprim=cprim, cbra=cbra,
-                         cap=cap, nq=len(key), quads=quads if cls == 3 else None,
+                         spans=kernel_chains(kern.terms()),
+                         cap=cap, nq=len(key), quads_all=quads,
                          k128=((quads[:, 0].astype(np.int64) * 128 + quads[:, 1]) * 128 + quads[:, 2]) * 128
                          + quads[:, 3]))
         log("I%d: %d quartets in %d groups" % (cls, len(key), len(groups)))
@@ -392,10 +497,14 @@ def main():
                     la, lb, lc, ld = lq
                     i5 = wk["cls"] == 5
                     npq = int(wk["cprim"][s1] - wk["cprim"][s0])
-                    fl = contraction_flops(la, lb, lc, ld, i5, npq, int(wk["cbra"][s1] - wk["cbra"][s0]), s1 - s0)
+                    nbp = int(wk["cbra"][s1] - wk["cbra"][s0])
+                    fl = method_flops(la, lb, lc, ld, i5, npq, nbp)
+                    flf = contraction_flops(la, lb, lc, ld, i5, npq, nbp, s1 - s0)
+                    L = la + lb + lc + ld + (2 if i5 else 0)
                     # algorithmic HBM bytes: blocks written, A_0..A_L read, four list entries per quartet
-                    nbytes = 8 * size + 8 * (la + lb + lc + ld + (2 if i5 else 0) + 1) * npq + 32 * (s1 - s0)
-                    record["launches"].append((kernel_name(la, lb, lc, ld, i5), fl, e0, e1, nbytes))
+                    nbytes = 8 * size + 8 * (L + 1) * npq + 32 * (s1 - s0)
+                    record["launches"].append((kernel_name(la, lb, lc, ld, i5), fl, e0, e1, nbytes, flf))
+                    record["aux_flops"].append(aux_flops(L, wk["spans"], npq))
             ev_cls1.record(st)
             if record is not None:
                 record["classes"].append((wk["cls"], nq, ev_cls0, ev_cls1))
@@ -409,7 +518,7 @@ def main():
         run_step(w % args.batches, None)
     torch.cuda.synchronize()
     f12int.stream_status()
-    rec = {"launches": [], "classes": [], "aux": []}
+    rec = {"launches": [], "classes": [], "aux": [], "aux_flops": []}
     t0 = time.perf_counter()
     nq_total = 0
     for s in range(args.steps):
@@ -429,18 +538,21 @@ def main():
 
     by_kernel = {}
     alg_bytes = 0
-    for (name, fl, e0, e1, nb) in rec["launches"]:
+    fl_fact = 0.0
+    for (name, fl, e0, e1, nb, flf) in rec["launches"]:
         d = by_kernel.setdefault(name, [0, 0.0, 0.0])
         d[0] += 1
         d[1] += fl
         d[2] += e0.elapsed_time(e1) / 1e3
         alg_bytes += nb
+        fl_fact += flf
     dom = max(by_kernel, key=lambda k: by_kernel[k][2])
     n_c = sum(v[0] for v in by_kernel.values())
     fl_c = sum(v[1] for v in by_kernel.values())
     contraction_time = sum(v[2] for v in by_kernel.values())
     achieved = fl_c / contraction_time / 1e12
     aux_time = sum(a.elapsed_time(b) / 1e3 for (a, b) in rec["aux"])
+    aux_fl = float(sum(rec["aux_flops"]))
     gpu_time = sum(v[1] for v in per_class.values())
 
     log("stored oracle sample")
@@ -452,17 +564,18 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        wk3 = [wk for wk in work if wk["cls"] == 3]
-        if wk3:
-            log("CPU oracle sample")
-            rate, used, nsamp, cores, rate1 = cpu_baseline(shells, wk3[0]["quads"])
-            log("CPU oracle: %.3g quartets/s on %d cores" % (rate, cores))
-            cpu = {"value": rate, "unit": "quartets/s", "cores": cores, "kind": "oracle",
-                   "value_one_core": rate1,
-                   "sample": "I3: %d quartets drawn uniformly from the 20-atom list among those with "
-                             "<= 4 primitive quartets, each time scaled to the list's mean primitive "
-                             "count; %.1f s of CPU work in %d worker processes, one per core"
-                             % (nsamp, used, cores)}
+        log("CPU oracle sample")
+        cb = cpu_baseline(work, ks)
+        log("CPU oracle: %.3g quartets/s on %d cores" % (cb["rate"], cb["cores"]))
+        cpu = {"value": cb["rate"], "unit": "quartets/s", "cores": cb["cores"], "kind": "oracle",
+               "value_one_core": cb["rate_one_core"],
+               "sample": "stratified by class (I2-I6) and primitive-count bin (1-4, 5-16, 17-64): %d quartets "
+                         "drawn uniformly per stratum from the 20-atom lists, %.0f s of CPU work in one worker "
+                         "process per core; stratum mean times weighted by the workload's quartet counts. "
+                         "Quartets with more than 64 primitive quartets are not sampled: the strata hold "
+                         "%.1f%% of the workload's quartets" % (cb["quartets_timed"], cb["cpu_seconds"],
+                                                                100 * cb["coverage"]),
+               "strata": cb["strata"]}
 
     line = {
         "metric": METRIC,
@@ -479,8 +592,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "20 atoms in a 12 bohr cube (seed 5070), s,s,p,p,d,f shells with 1-6 "
-                        "primitives, all unique quartets of I2-I6 (factor P1), one of %d stratified "
-                        "batches per step" % args.batches,
+                        "primitives, %s of I2-I6 (factor P1), one of %d stratified batches per step"
+                        % ("the unique quartets kept by the %.0e screen" % args.screen_tol if args.screen_tol > 0
+                           else "all unique quartets", args.batches),
+            "screen_tol": args.screen_tol,
+            "quartets_in_lists": {"I%d" % wk["cls"]: wk["nq"] for wk in work},
             "classes": ["I%d" % c for c in classes],
             "streams": ("one per class, concurrent (per-class rates overlap)" if args.concurrent else "one")
                        + ("; radial derivatives of the next slice overlap the contraction" if args.pipeline else ""),
@@ -497,6 +613,12 @@ def main():
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE x %.4f + WRITE_SIZE x %.4f)"
                             % (TRAFFIC_RECORD["fetch_scale"], TRAFFIC_RECORD["write_scale"]),
+            "flops_per_launch_count": "method count: per primitive quartet 3 C(L+4,4) (R) + 2 H_ab H_cd n_cd "
+                                      "(ket); per bra primitive pair 2 n_ab H_ab n_cd x E^ab nonzero fraction "
+                                      "(bra); I5 4x ket and bra, R at L+2",
+            "factorised_passes": {"flops_per_launch": fl_fact / n_c,
+                                  "achieved": fl_fact / contraction_time / 1e12,
+                                  "frac": fl_fact / contraction_time / 1e12 / FP64_VECTOR_PEAK_TFLOPS},
             "algorithmic_bytes_per_launch": alg_bytes / n_c,
             "hardware_fp64": None if not rec_ok else {
                 "flops_per_launch": TRAFFIC_RECORD["contraction_hw_fp64_flops_per_launch"],
@@ -513,6 +635,12 @@ def main():
                 "achieved": by_kernel[dom][1] / by_kernel[dom][2] / 1e12},
             "aux_kernel": {"launches": len(rec["aux"]), "avg_launch_ms": aux_time / max(len(rec["aux"]), 1) * 1e3,
                            "share_of_gpu_time": aux_time / gpu_time, "traffic": aux_traffic,
+                           "flops_per_launch": aux_fl / max(len(rec["aux"]), 1),
+                           "achieved": aux_fl / aux_time / 1e12,
+                           "frac": aux_fl / aux_time / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                           "flops_count": "per chain and sign a ladder start (%d flops) + 6 (L + span); per sign "
+                                          "8 (L+1)(L+2)(2L+3)/6 for the radial-derivative recursion"
+                                          % AUX_START_FLOPS,
                            "hardware_fp64_achieved": None if not rec_ok else
                            TRAFFIC_RECORD["aux_hw_fp64_flops_per_launch"] / (aux_time / max(len(rec["aux"]), 1)) / 1e12},
         },

@@ -122,9 +122,17 @@ void f12_kernel_destroy(f12_kernel *k);
  * bra pair index >= the ket pair index (8-fold symmetry); for I5 every
  * (bra, ket) combination (no bra-ket symmetry; (ba|cd) = -(ab|cd) and
  * (ab|dc) = (ab|cd) give the remaining blocks).
- * If screen_tol > 0 a quartet is kept when Q_ab Q_cd >= screen_tol with
- * Q_ab = sqrt(max |(ab|k|ab)|) evaluated with `screen_kernel` (use an I3
- * kernel for I5); screen_kernel may be NULL when screen_tol <= 0.
+ * If screen_tol > 0 a quartet is kept when its size estimate reaches
+ * screen_tol.  The estimate is Q_ab Q_cd, Q_ab = sqrt(max |(ab|k|ab)|)
+ * evaluated with `screen_kernel` (the class's kernel; an I3 kernel for I5),
+ * times the growth of the kernel's undamped terms c r^alpha e^{b r} (b > 0,
+ * the long-range part of Eq. (rs12)) from r = 1 to the largest distance
+ * between the pairs' product centres, times exp(b sqrt((l_a+l_b+1)/(2 p_min))
+ * + b^2/(4 p_min)) per pair for the extent of its density (p_min the
+ * smallest exponent sum of the pair); for I5 the bra factor also carries the
+ * largest bra exponent times (2 l_max + 3) (Eq. (I5_)).  It is an estimate,
+ * not a proven bound: Schwarz's inequality does not hold for a kernel that
+ * grows with r.  screen_kernel may be NULL when screen_tol <= 0.
  * The public order (offsets, output, f12_quartet_list) groups the quartets
  * by (l_a, l_b, l_c, l_d) and, inside a group, orders them by decreasing
  * number of primitive quartets (enumeration order among equal counts). */

@@ -73,6 +73,9 @@ struct f12_pairs {
   // host copies used for enumeration
   std::vector<int32_t> sa, sb, la, lb, ka, kb;
   std::vector<int64_t> pp_off;
+  // per shell pair, for the screening estimate: midpoint of A and B, |A - B|,
+  // smallest exponent sum a + b and largest exponent over the primitive pairs
+  std::vector<double> midx, midy, midz, ablen, pmin, emax;
   DevBuf<int32_t> d_sa, d_sb, d_la, d_lb, d_ka, d_kb;
   DevBuf<int64_t> d_pp_off;
   DevBuf<double> d_ABx, d_ABy, d_ABz;
@@ -228,6 +231,24 @@ extern "C" int f12_pairs_build(const f12_basis *basis, int32_t ordered, void *st
       ABx.push_back(A[0] - B[0]);
       ABy.push_back(A[1] - B[1]);
       ABz.push_back(A[2] - B[2]);
+      P->midx.push_back(0.5 * (A[0] + B[0]));
+      P->midy.push_back(0.5 * (A[1] + B[1]));
+      P->midz.push_back(0.5 * (A[2] + B[2]));
+      P->ablen.push_back(std::sqrt((A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) +
+                                   (A[2] - B[2]) * (A[2] - B[2])));
+      {
+        double amin = 1e300, bmin = 1e300, em = 0.0;
+        for (int ia = 0; ia < a.nprim; ++ia) {
+          amin = std::min(amin, basis->exps[a.first_prim + ia]);
+          em = std::max(em, basis->exps[a.first_prim + ia]);
+        }
+        for (int ib = 0; ib < b.nprim; ++ib) {
+          bmin = std::min(bmin, basis->exps[b.first_prim + ib]);
+          em = std::max(em, basis->exps[b.first_prim + ib]);
+        }
+        P->pmin.push_back(amin + bmin);
+        P->emax.push_back(em);
+      }
       for (int ia = 0; ia < a.nprim; ++ia)
         for (int ib = 0; ib < b.nprim; ++ib) {
           pp_sa.push_back(i);
@@ -751,13 +772,16 @@ namespace {
 int finish_quartets(f12_quartets *Q, std::vector<int64_t> &qb, std::vector<int64_t> &qk) {
   const f12_pairs *B = Q->bra, *K = Q->ket;
   const int64_t nq = (int64_t)qb.size();
-  // bin by (la, lb, lc, ld) with a counting sort (stable)
+  // bin by (la, lb, lc, ld) with a counting sort (stable); one digit of radix
+  // LMAX + 1 per angular momentum
+  constexpr int RAD = LMAX + 1, NBIN = RAD * RAD * RAD * RAD;
+  static_assert(F12_LMAX == LMAX, "public and internal angular-momentum limits agree");
   auto key = [&](int64_t i) {
-    return ((B->la[qb[i]] * 4 + B->lb[qb[i]]) * 4 + K->la[qk[i]]) * 4 + K->lb[qk[i]];
+    return ((B->la[qb[i]] * RAD + B->lb[qb[i]]) * RAD + K->la[qk[i]]) * RAD + K->lb[qk[i]];
   };
-  std::vector<int64_t> cnt(257, 0);
+  std::vector<int64_t> cnt(NBIN + 1, 0);
   for (int64_t i = 0; i < nq; ++i) cnt[key(i) + 1]++;
-  for (int k = 0; k < 256; ++k) cnt[k + 1] += cnt[k];
+  for (int k = 0; k < NBIN; ++k) cnt[k + 1] += cnt[k];
   std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
   Q->qb.assign(nq, 0);
   Q->qk.assign(nq, 0);
@@ -774,7 +798,7 @@ int finish_quartets(f12_quartets *Q, std::vector<int64_t> &qb, std::vector<int64
   // the longest work-groups of a launch start first
   {
     std::vector<int64_t> idx, tb, tk;
-    for (int k = 0; k < 256; ++k) {
+    for (int k = 0; k < NBIN; ++k) {
       const int64_t lo = cnt[k], n = cnt[k + 1] - cnt[k];
       if (n < 2) continue;
       idx.resize(n);
@@ -794,10 +818,10 @@ int finish_quartets(f12_quartets *Q, std::vector<int64_t> &qb, std::vector<int64
     }
   }
   Q->bins.clear();
-  for (int k = 0; k < 256; ++k) {
+  for (int k = 0; k < NBIN; ++k) {
     int64_t n = cnt[k + 1] - cnt[k];
     if (n == 0) continue;
-    Q->bins.push_back({k >> 6, (k >> 4) & 3, (k >> 2) & 3, k & 3, cnt[k], n});
+    Q->bins.push_back({k / (RAD * RAD * RAD), (k / (RAD * RAD)) % RAD, (k / RAD) % RAD, k % RAD, cnt[k], n});
   }
   Q->qoff.assign(nq + 1, 0);
   Q->qprim.assign(nq + 1, 0);
@@ -909,10 +933,57 @@ extern "C" int f12_quartets_build(const f12_pairs *bra, const f12_pairs *ket, in
   Q->cls = cls;
   std::vector<int64_t> qb, qk;
   const bool fold = (cls != 5);  // I5 has no bra-ket symmetry
+  // Screening estimate.  Q_ab Q_cd alone bounds |(ab|k|cd)| only for a
+  // positive-definite kernel; the long-range part c0 r^rho e^{B r} of
+  // Eq. (rs12) grows with r, so the estimate carries the growth of the
+  // kernel's undamped terms (g = 0, b > 0),
+  //   kappa(r) = sum |c_t| r^(alpha_t - 1) e^(b_t r),
+  // from r = 1 to the largest distance R_eff between the primitive-pair
+  // centres of the two pairs (each P lies on its segment AB), and per pair
+  // the growth of e^{b |r - P|} over the pair density's extent,
+  //   exp(b sqrt((l_a + l_b + 1) / (2 p_min)) + b^2 / (4 p_min)).
+  // I5 = 1/2 (lap_A - lap_B) I3 (Eq. (I5_)) multiplies the bra by up to about
+  // the largest bra exponent times (2 l + 3).
+  std::vector<HostTerm> grow;
+  double bmax = 0.0;
+  if (screen_tol > 0)
+    for (const HostTerm &t : screen_kernel->terms)
+      if (t.g == 0.0 && t.b > 0.0) {
+        grow.push_back(t);
+        bmax = std::max(bmax, t.b);
+      }
+  auto kappa = [&](double r) {
+    double v = 0.0;
+    for (const HostTerm &t : grow) v += std::fabs(t.c) * std::pow(r, t.alpha - 1.0) * std::exp(t.b * r);
+    return v;
+  };
+  const double kappa1 = grow.empty() ? 1.0 : kappa(1.0);
+  auto pair_factor = [&](const f12_pairs *P, int64_t i, bool i5bra) {
+    const double pm = P->pmin[i];
+    double f = std::exp(bmax * std::sqrt((P->la[i] + P->lb[i] + 1) / (2.0 * pm)) + bmax * bmax / (4.0 * pm));
+    if (i5bra) f *= P->emax[i] * (2 * std::max(P->la[i], P->lb[i]) + 3);
+    return f;
+  };
+  std::vector<double> Sb, Sk;
+  if (screen_tol > 0) {
+    Sb.resize(bra->nsp);
+    Sk.resize(ket->nsp);
+    for (int64_t b = 0; b < bra->nsp; ++b) Sb[b] = Qb[b] * pair_factor(bra, b, cls == 5);
+    for (int64_t k = 0; k < ket->nsp; ++k) Sk[k] = Qk[k] * pair_factor(ket, k, false);
+  }
   for (int64_t b = 0; b < bra->nsp; ++b) {
     int64_t kmax = fold ? std::min(b, ket->nsp - 1) : ket->nsp - 1;
     for (int64_t k = 0; k <= kmax; ++k) {
-      if (screen_tol > 0 && Qb[b] * Qk[k] < screen_tol) continue;
+      if (screen_tol > 0) {
+        double est = Sb[b] * Sk[k];
+        if (est < screen_tol && !grow.empty()) {
+          const double dx = bra->midx[b] - ket->midx[k], dy = bra->midy[b] - ket->midy[k],
+                       dz = bra->midz[b] - ket->midz[k];
+          const double reff = std::sqrt(dx * dx + dy * dy + dz * dz) + 0.5 * (bra->ablen[b] + ket->ablen[k]);
+          if (reff > 1.0) est *= std::max(1.0, kappa(reff) / kappa1);
+        }
+        if (est < screen_tol) continue;
+      }
       qb.push_back(b);
       qk.push_back(k);
     }

@@ -16,6 +16,12 @@ Sets:
   plain20  quartets sampled from the 20-atom molecule (seed 5070), stratified
            by total angular momentum, restricted to at most 64 primitive
            quartets so that the oracle finishes; classes I2-I6, P1.
+  tinyall  every unique quartet of the 3-atom s+p molecule (seed 1412): the 231
+           quartets (bra pair index >= ket pair index) of I1-I4 and I6 and the
+           441 (bra, ket) combinations of unordered pairs of I5, factor set P1.
+  deephl   deep high-l contractions (deephl_shells): (dd|dd), (dd|ff), (fd|ff)
+           and (ff|ff) with 36 ket primitive pairs, (ff|ff) and (fd|fd) with 36
+           bra primitive pairs, and (sp|dd) with 1e4 exponents; I2-I6, P1.
   factors  the 3-atom s+p molecule (seed 1412) with the other factor sets:
            P2 (non-integer rho < -1) for I2, I3, I5; P4 (integer rho >= 0)
            for I2-I6; the mixed pair (f, f') = (P1, P4) for I4 and I6; I3
@@ -61,6 +67,42 @@ def deep_shells():
         co = rng.uniform(0.1, 1.0, K)
         out.append(Shell(pos[i], l, ex, co, i))
     return out
+
+
+def deephl_shells():
+    """Six shells on three centres (seed 4343, 3 bohr cube): f(1) d(1) on the
+    first, f(6) d(6) on the second (exponents log-uniform in [0.1, 10]), s(6)
+    p(6) on the third with one exponent 1e4 each and the rest log-uniform in
+    [0.1, 50]."""
+    from synth.molecules import Shell
+    rng = np.random.default_rng(4343)
+    pos = rng.uniform(0.0, 3.0, (3, 3))
+    spec = [(3, 1, 0), (2, 1, 0), (3, 6, 1), (2, 6, 1), (0, 6, 2), (1, 6, 2)]
+    out = []
+    for l, K, at in spec:
+        hi = 50.0 if at == 2 else 10.0
+        ex = 10.0 ** rng.uniform(-1.0, np.log10(hi), K)
+        if at == 2:
+            ex[0] = 1.0e4
+        co = rng.uniform(0.1, 1.0, K)
+        out.append(Shell(pos[at], l, ex, co, at))
+    return out
+
+
+# shells: 0 f(1), 1 d(1) | 2 f(6), 3 d(6) | 4 s(6), 5 p(6) with 1e4 exponents
+DEEPHL_QUADS = [(1, 1, 3, 3), (1, 1, 2, 2), (0, 1, 2, 2), (0, 0, 2, 2), (2, 2, 0, 0), (2, 3, 0, 1), (4, 5, 3, 1)]
+
+
+def tiny_pairs():
+    return [(i, j) for i in range(6) for j in range(i + 1)]
+
+
+def tinyall_quads(cls):
+    """All unique quartets of the tiny molecule as f12_quartets_build lists them."""
+    pr = tiny_pairs()
+    if cls == 5:
+        return [a + c for a in pr for c in pr]
+    return [pr[b] + pr[k] for b in range(len(pr)) for k in range(b + 1)]
 
 
 # (s2 s2|s6 p6): 36 ket primitive pairs; (s2 s2|s16 s16): 256; (p16 s2|s6 s6): 16-primitive bra shell
@@ -111,7 +153,12 @@ def _job(args):
         sh = [tiny_config()[1][i].as_dict() for i in quad]
         return args, np.asarray(integrals.contracted(cls, *sh, FACTOR_SETS[f], FACTOR_SETS[fp]),
                                 dtype=np.float64).ravel()
-    shells = {"df3": df3_shells, "deep": deep_shells}.get(setname, lambda: config_plain()[1])()
+    if setname == "tinyall":
+        from synth import tiny_config
+        shells = tiny_config()[1]
+    else:
+        shells = {"df3": df3_shells, "deep": deep_shells, "deephl": deephl_shells}.get(
+            setname, lambda: config_plain()[1])()
     sh = [shells[i].as_dict() for i in quad]
     return args, np.asarray(integrals.contracted(cls, *sh, P1, P1), dtype=np.float64).ravel()
 
@@ -123,6 +170,10 @@ def build(setname):
         jobs += [(setname, 3, q) for q in DF3_QUADS_I5 if q not in DF3_QUADS]
     elif setname == "deep":
         jobs = [(setname, c, q) for c in (5, 3, 6) for q in DEEP_QUADS]
+    elif setname == "tinyall":
+        jobs = [(setname, c, q) for c in (5, 1, 2, 3, 4, 6) for q in tinyall_quads(c)]
+    elif setname == "deephl":
+        jobs = [(setname, c, q) for c in (5, 2, 3, 4, 6) for q in DEEPHL_QUADS]
     elif setname == "factors":
         cases = list(FACTOR_CASES) + [(3, f, fp) for (c, f, fp) in FACTOR_CASES if c == 5]
         jobs = [(setname, c, q, f, fp) for (c, f, fp) in cases for q in FACTOR_QUADS]

@@ -2,6 +2,10 @@
 its ctypes binding, the oracle for expected values)."""
 import numpy as np
 
+# Block-relative tolerance of the FP64 path: max |I_gpu - I_ref| / max |I_ref|
+# over one contracted-quartet block.
+REL_TOL = 1e-12
+
 
 def block_rel_err(got, ref):
     """max |got - ref| / max |ref| over one contracted-quartet block."""
@@ -9,6 +13,41 @@ def block_rel_err(got, ref):
     if scale == 0:
         return float(np.max(np.abs(got)))
     return float(np.max(np.abs(got - ref)) / scale)
+
+
+def i5_vanishes(la, same_shell):
+    """An I5 block vanishes identically when the bra pair is one s or p shell
+    taken twice: for l <= 1 the Laplacian of each component x_c e^{-a r^2} is
+    x_c h(r) with one h for all components, so
+    (lap phi_i) phi_j - phi_i (lap phi_j) = 0 pointwise.  For d and f shells
+    the components are not harmonic and the block does not vanish."""
+    return same_shell and la <= 1
+
+
+def vanishes_by_parity(quad, shells):
+    """A block vanishes identically when its four shells sit on one centre and
+    l_a + l_b + l_c + l_d is odd: inversion through that centre maps the
+    integrand to minus itself (the kernel depends on r12 only)."""
+    cs = {tuple(np.round(np.asarray(shells[i].center, float), 12)) for i in quad}
+    return len(cs) == 1 and sum(shells[i].l for i in quad) % 2 == 1
+
+
+def zero_block_err(got, diag_ab, diag_cd):
+    """Error of a block that vanishes identically, on the scale
+    sqrt(max |(ab|ab)| max |(cd|cd)|) of its pairs (Schwarz-like size of the
+    terms that cancel): the GPU's rounding noise over that scale."""
+    return float(np.max(np.abs(got))) / np.sqrt(diag_ab * diag_cd)
+
+
+def i5_block_err(got, ref_i5, ref_i3, bra_exps, vanishes):
+    """Block-relative error of an I5 block on its own scale max |I5|.  Only
+    for a block that vanishes identically (i5_vanishes) is the GPU's rounding
+    noise scored against the size of the terms that cancel, the largest bra
+    exponent times max |I3| of the same quartet."""
+    if vanishes:
+        scale = float(np.max(bra_exps)) * float(np.max(np.abs(ref_i3)))
+        return float(np.max(np.abs(got - ref_i5)) / scale)
+    return block_rel_err(got, ref_i5)
 
 
 def run_quads(f12int, basis, pairs, kernel, cls, quads):
@@ -27,6 +66,17 @@ def run_quads(f12int, basis, pairs, kernel, cls, quads):
     return res
 
 
+def run_list(f12int, Q, kernel):
+    """Evaluate a whole quartet list; returns {tuple(quad): block}."""
+    import torch
+    out = torch.empty(max(Q.n_out, 1), dtype=torch.float64, device="cuda")
+    f12int.eval_into(Q, kernel, out)
+    f12int.stream_status()
+    host = out.cpu().numpy()
+    offs = Q.offsets()
+    return {tuple(int(v) for v in qd): host[offs[i]:offs[i + 1]] for i, qd in enumerate(Q.quads())}
+
+
 def envelope_err(A, ref, xi):
     """Errors of radial derivatives on their natural scale: |dA_n|/(2 xi)^n
     relative to max_k |A_k|/(2 xi)^k (A_n grows like (2 xi)^n; single A_n can
@@ -35,29 +85,3 @@ def envelope_err(A, ref, xi):
     sc = (2.0 * np.asarray(xi))[:, None] ** np.arange(L + 1)[None, :]
     env = np.max(np.abs(ref) / sc, axis=1)[:, None]
     return np.abs(A - ref) / sc / env
-
-
-def i5_block_err(got, ref_i5, ref_i3, bra_exps):
-    """I5 = 1/2 (lap_A - lap_B) I3 has the magnitude of (exponent x I3); a
-    bra pair built from one shell gives a block that vanishes identically
-    (lap x_c = x g(r), lap y_c = y g(r) with the same g), so the block is
-    scored against max(max|I5|, max bra exponent * max|I3|)."""
-    scale = max(np.max(np.abs(ref_i5)), float(np.max(bra_exps)) * np.max(np.abs(ref_i3)))
-    return float(np.max(np.abs(got - ref_i5)) / scale)
-
-
-# Blocks whose largest |integral| is below the workloads' screening threshold
-# (1e-12) are negligible; there the MD sums in binary64 can cancel by 1e4 and
-# more, so they are held to an absolute bound of 1e-12 of that threshold.
-NEGLIGIBLE = 1e-12
-ABS_FLOOR = 1e-24
-
-
-def block_ok(got, ref, rel_tol=1e-12):
-    """(passes, relative error, absolute error) under the rule above."""
-    scale = float(np.max(np.abs(ref)))
-    abs_err = float(np.max(np.abs(got - ref)))
-    rel = abs_err / scale if scale > 0 else abs_err
-    if scale >= NEGLIGIBLE:
-        return rel < rel_tol, rel, abs_err
-    return rel < rel_tol or abs_err < ABS_FLOOR, rel, abs_err

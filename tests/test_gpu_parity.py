@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 
 from synth import FACTOR_SETS, tiny_config
-from tests.gpu_common import block_ok, block_rel_err, envelope_err, i5_block_err, run_quads
+from tests.gpu_common import (REL_TOL, block_rel_err, envelope_err, i5_block_err, i5_vanishes, run_list,
+                              run_quads, vanishes_by_parity, zero_block_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -145,11 +146,12 @@ def test_tiny_blocks_vs_oracle(lib, cls):
         ref = integrals.contracted(cls, *sh, P1, P1).ravel()
         if cls == 5:
             ref3 = integrals.contracted(3, *sh, P1, P1).ravel()
-            e = i5_block_err(got[qd], ref, ref3, np.concatenate([sh[0]["exps"], sh[1]["exps"]]))
+            e = i5_block_err(got[qd], ref, ref3, np.concatenate([sh[0]["exps"], sh[1]["exps"]]),
+                             i5_vanishes(shells[qd[0]].l, qd[0] == qd[1]))
         else:
             e = block_rel_err(got[qd], ref)
         print(f"  {qd} err {e:.2e}", flush=True)
-        assert e < 1e-12, (qd, e)
+        assert e < REL_TOL, (qd, e)
 
 
 def _golden(name):
@@ -171,12 +173,12 @@ def _check_golden_set(lib, shells, golden, cls, quads):
         if cls == 5:
             ref3 = golden["c3_%d_%d_%d_%d" % tuple(qd)]
             bra_exps = np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps])
-            e = i5_block_err(got[qd], ref, ref3, bra_exps)
+            e = i5_block_err(got[qd], ref, ref3, bra_exps, i5_vanishes(shells[qd[0]].l, qd[0] == qd[1]))
         else:
             e = block_rel_err(got[qd], ref)
         worst = max(worst, e)
-        print(f"  {qd} l={[shells[i].l for i in qd]} err {e:.2e}", flush=True)
-        assert e < 1e-12, (qd, e)
+        print(f"  {qd} l={[shells[i].l for i in qd]} max|I| {np.max(np.abs(ref)):.1e} err {e:.2e}", flush=True)
+        assert e < REL_TOL, (qd, e)
     return worst
 
 
@@ -195,7 +197,10 @@ def test_plain20_sampled_vs_golden(lib, cls):
     """The 20-atom workload at full size: the class's whole unique-quartet
     list is built as bench.py builds it, and the stored oracle values of
     quartets sampled from it (two per total angular momentum, at most 64
-    primitive quartets each) are compared with f12_eval on those entries."""
+    primitive quartets each) are compared with f12_eval on those entries,
+    block-relative.  The screened list at 1e-12 is built as well: every
+    sampled block it keeps must meet the 1e-12 block-relative bound, and every
+    block it drops must be below 1e-12."""
     import os
     import torch
     sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
@@ -206,13 +211,17 @@ def test_plain20_sampled_vs_golden(lib, cls):
     basis = lib.Basis.from_shells(shells)
     pairs = lib.Pairs(basis, 0)
     k = lib.Kernel(cls, P1, P1)
+    ks = lib.Kernel(3, P1, P1) if cls == 5 else k
     Q = lib.Quartets.build(pairs, pairs, cls)
     quads = Q.quads().astype(np.int64)
     offs = Q.offsets()
     keys = ((quads[:, 0] * 128 + quads[:, 1]) * 128 + quads[:, 2]) * 128 + quads[:, 3]
+    Qs = lib.Quartets.build(pairs, pairs, cls, screen_tol=1e-12, screen_kernel=ks)
+    sq = Qs.quads().astype(np.int64)
+    kept = set((((sq[:, 0] * 128 + sq[:, 1]) * 128 + sq[:, 2]) * 128 + sq[:, 3]).tolist())
     sample = plain20_quads()
-    print(f"plain20 cls={cls} list={len(keys)} samples={len(sample)}", flush=True)
-    worst = 0.0
+    print(f"plain20 cls={cls} list={len(keys)} screened={len(sq)} samples={len(sample)}", flush=True)
+    bad = []
     for qd in sample:
         key = ((qd[0] * 128 + qd[1]) * 128 + qd[2]) * 128 + qd[3]
         idx = np.nonzero(keys == key)[0]
@@ -225,22 +234,25 @@ def test_plain20_sampled_vs_golden(lib, cls):
         ref = golden["c%d_%d_%d_%d_%d" % ((cls,) + tuple(qd))]
         if cls == 5:
             ref3 = golden["c3_%d_%d_%d_%d" % tuple(qd)]
-            e = i5_block_err(got, ref, ref3, np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps]))
-            ok = e < 1e-12 or (np.max(np.abs(ref3)) < 1e-12 and np.max(np.abs(got - ref)) < 1e-24)
-            ea = float(np.max(np.abs(got - ref)))
+            e = i5_block_err(got, ref, ref3, np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps]),
+                             i5_vanishes(shells[qd[0]].l, qd[0] == qd[1]))
         else:
-            ok, e, ea = block_ok(got, ref)
-        worst = max(worst, e)
-        note = "" if e < 1e-12 else " (negligible block: max|I| %.1e, abs err %.1e)" % (np.max(np.abs(ref)), ea)
-        print(f"  {qd} l={[shells[j].l for j in qd]} err {e:.2e}{note}", flush=True)
-        assert ok, (qd, e, ea)
+            e = block_rel_err(got, ref)
+        mx = float(np.max(np.abs(ref)))
+        in_screen = key in kept
+        print(f"  {qd} l={[shells[j].l for j in qd]} max|I| {mx:.1e} err {e:.2e} "
+              f"{'kept' if in_screen else 'dropped'} by the 1e-12 screen", flush=True)
+        if (in_screen and e >= REL_TOL) or (not in_screen and mx >= 1e-12):
+            bad.append((qd, mx, e, in_screen))
+    assert not bad, bad
 
 
 @pytest.mark.parametrize("cls", [3, 5])
-def test_schwarz_screening(lib, cls):
-    """f12_quartets_build with screen_tol keeps exactly the quartets with
-    Q_ab Q_cd >= tol, Q_ab = sqrt(max |(ab|k3|ab)|) (diagonal blocks evaluated
-    here through an explicit list), and kept blocks equal the unscreened ones."""
+def test_screening_keeps_schwarz_and_equal_blocks(lib, cls):
+    """f12_quartets_build with screen_tol keeps at least the quartets with
+    Q_ab Q_cd >= tol (Q_ab = sqrt(max |(ab|k3|ab)|), diagonal blocks evaluated
+    here through an explicit list), kept blocks equal the unscreened ones bit
+    for bit, and every dropped block is below tol."""
     import os
     import torch
     sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
@@ -261,21 +273,50 @@ def test_schwarz_screening(lib, cls):
     scr = lib.Quartets.build(pairs, pairs, cls, screen_tol=tol, screen_kernel=k3)
     fq = [tuple(int(v) for v in r) for r in full.quads()]
     sq = [tuple(int(v) for v in r) for r in scr.quads()]
-    expect = [q for q in fq if Qab[(q[0], q[1])] * Qab[(q[2], q[3])] >= tol]
-    print(f"screening cls={cls} tol={tol:.3e} full={len(fq)} kept={len(sq)}", flush=True)
-    assert sq == expect
+    schwarz = [q for q in fq if Qab[(q[0], q[1])] * Qab[(q[2], q[3])] >= tol]
+    print(f"screening cls={cls} tol={tol:.3e} full={len(fq)} kept={len(sq)} schwarz={len(schwarz)}", flush=True)
+    assert set(schwarz) <= set(sq)
     assert 0 < len(sq) < len(fq)
-    out_f = torch.empty(full.n_out, dtype=torch.float64, device="cuda")
-    out_s = torch.empty(scr.n_out, dtype=torch.float64, device="cuda")
-    lib.eval_into(full, k, out_f)
-    lib.eval_into(scr, k, out_s)
-    lib.stream_status()
-    hf, hs = out_f.cpu().numpy(), out_s.cpu().numpy()
-    of, os_ = full.offsets(), scr.offsets()
-    pos = {q: i for i, q in enumerate(fq)}
-    for i, q in enumerate(sq):
-        j = pos[q]
-        assert np.array_equal(hs[os_[i]:os_[i + 1]], hf[of[j]:of[j + 1]]), q
+    hf = run_list(lib, full, k)
+    hs = run_list(lib, scr, k)
+    for q in sq:
+        assert np.array_equal(hs[q], hf[q]), q
+    kept = set(sq)
+    worst = max(float(np.max(np.abs(hf[q]))) for q in fq if q not in kept)
+    print(f"  largest dropped block {worst:.3e}", flush=True)
+    assert worst < tol
+
+
+@pytest.mark.parametrize("cls", [2, 3, 4, 6, 5])
+def test_screening_estimate_on_spread_molecule(lib, cls):
+    """On 8 atoms spread through a 20 bohr cube (s, p, d shells, 1-3
+    primitives, exponents log-uniform in [0.05, 50]) every quartet that the
+    screen drops at tol = 1e-12, 1e-9, 1e-6 is below tol (all blocks computed
+    unscreened).  The long-range part of the factor grows like e^{B r}, so the
+    product Q_ab Q_cd alone would drop blocks far above tol: those are
+    counted and printed."""
+    from synth import molecule
+    _, shells = molecule(6061, 8, 20.0, 1.5, (0, 1, 2), 1, 3, 0.05, 50.0)
+    basis = lib.Basis.from_shells(shells)
+    pairs = lib.Pairs(basis, 0)
+    k = lib.Kernel(cls, P1, P1)
+    ks = lib.Kernel(3, P1, P1) if cls == 5 else k
+    full = lib.Quartets.build(pairs, pairs, cls)
+    hf = run_list(lib, full, k)
+    mx = {q: float(np.max(np.abs(v))) for q, v in hf.items()}
+    ns = len(shells)
+    upairs = [(i, j) for i in range(ns) for j in range(i + 1)]
+    dg = run_quads(lib, basis, lib.Pairs(basis, 1), ks, 3 if cls == 5 else cls, [(i, j, i, j) for (i, j) in upairs])
+    Qab = {(i, j): math.sqrt(float(np.max(np.abs(dg[(i, j, i, j)])))) for (i, j) in upairs}
+    for tol in (1e-12, 1e-9, 1e-6):
+        scr = lib.Quartets.build(pairs, pairs, cls, screen_tol=tol, screen_kernel=ks)
+        kept = set(tuple(int(v) for v in r) for r in scr.quads())
+        dropped = [q for q in mx if q not in kept]
+        worst = max((mx[q] for q in dropped), default=0.0)
+        plain_bad = sum(1 for q in mx if Qab[q[:2]] * Qab[q[2:]] < tol and mx[q] >= tol)
+        print(f"spread cls={cls} tol={tol:.0e}: {len(mx)} quartets, kept {len(kept)}, "
+              f"largest dropped {worst:.2e}; Q_ab Q_cd alone would drop {plain_bad} blocks >= tol", flush=True)
+        assert worst < tol, (tol, worst)
 
 
 def _factor_cases():
@@ -304,12 +345,71 @@ def test_factor_sets_vs_golden(lib, cls, f, fp):
         ref = golden[factor_key(cls, f, fp, qd)]
         if cls == 5:
             ref3 = golden[factor_key(3, f, fp, qd)]
-            e = i5_block_err(got[qd], ref, ref3, np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps]))
-            ok = e < 1e-12
+            e = i5_block_err(got[qd], ref, ref3, np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps]),
+                             i5_vanishes(shells[qd[0]].l, qd[0] == qd[1]))
         else:
-            ok, e, _ = block_ok(got[qd], ref)
-        print(f"  {qd} err {e:.2e}", flush=True)
-        assert ok, (qd, e)
+            e = block_rel_err(got[qd], ref)
+        print(f"  {qd} max|I| {np.max(np.abs(ref)):.1e} err {e:.2e}", flush=True)
+        assert e < REL_TOL, (qd, e)
+
+
+@pytest.mark.parametrize("cls", [1, 2, 3, 4, 6, 5])
+def test_tiny_all_quartets_vs_golden(lib, cls):
+    """Every unique quartet of the 3-atom s+p molecule (231 for I1-I4 and I6,
+    441 for I5), evaluated as one list built by f12_quartets_build, against
+    stored oracle values."""
+    import os
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import tinyall_quads
+    golden = _golden("tinyall")
+    shells = _tiny()
+    basis = lib.Basis.from_shells(shells)
+    pairs = lib.Pairs(basis, 0)
+    k = lib.Kernel(cls, P1, P1)
+    Q = lib.Quartets.build(pairs, pairs, cls)
+    got = run_list(lib, Q, k)
+    expect = tinyall_quads(cls)
+    print(f"tinyall cls={cls} quartets={len(got)}", flush=True)
+    assert sorted(got) == sorted(expect)
+    def diag(a, b):
+        # max |(ab|ab)| of the class's kernel (I3 for I5, times the largest bra
+        # exponent: the scale of the Laplacian terms)
+        c = 3 if cls == 5 else cls
+        v = float(np.max(np.abs(golden["c%d_%d_%d_%d_%d" % (c, a, b, a, b)])))
+        if cls == 5:
+            v *= float(max(np.max(shells[a].exps), np.max(shells[b].exps)))
+        return v
+
+    worst, worst_zero, bad, nzero = 0.0, 0.0, [], 0
+    for qd in expect:
+        ref = golden["c%d_%d_%d_%d_%d" % ((cls,) + tuple(qd))]
+        a, b, c, d = qd
+        if vanishes_by_parity(qd, shells) or (cls == 5 and i5_vanishes(shells[a].l, a == b)):
+            e = zero_block_err(got[qd], diag(a, b), diag(c, d) if cls != 5 else diag(c, d) /
+                               float(max(np.max(shells[c].exps), np.max(shells[d].exps))))
+            worst_zero = max(worst_zero, e)
+            nzero += 1
+        else:
+            e = block_rel_err(got[qd], ref)
+            worst = max(worst, e)
+        if e >= REL_TOL:
+            bad.append((qd, e))
+    print(f"  worst block-relative error {worst:.2e}; {nzero} blocks that vanish identically, "
+          f"largest |I_gpu| on their pairs' scale {worst_zero:.2e}", flush=True)
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("cls", [2, 3, 4, 6, 5])
+def test_deep_high_l_vs_golden(lib, cls):
+    """(dd|dd), (dd|ff), (fd|ff), (ff|ff) with 36 ket primitive pairs (more
+    than one staging chunk of 32), (ff|ff) and (fd|fd) with 36 bra primitive
+    pairs, and (sp|dd) with 1e4 exponents, against stored oracle values; for
+    I5 these run both forms of the contraction (the Laplacian-folded bra and
+    the four-component form of the largest shapes)."""
+    import os
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import DEEPHL_QUADS, deephl_shells
+    _check_golden_set(lib, deephl_shells(), _golden("deephl"), cls, DEEPHL_QUADS)
 
 
 @pytest.mark.parametrize("cls", [3, 5, 6])
