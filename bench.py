@@ -350,6 +350,173 @@ def stored_sample_errors(work, shells):
 
 
 # ---------------------------------------------------------------------------
+def batched_main(args):
+    """The batching workload: the 20-atom molecule (seed 5070) and two more of
+    the same recipe and density (10 atoms in 9.5 bohr, seed 5071; 35 atoms in
+    14.4 bohr, seed 5072), every unique quartet kept by the 1e-12 screen, all
+    shapes from (ss|ss) to (ff|ff).  Lists are built on the device.  Step s
+    takes slice (s + g) mod --slices of every shape group g of every list, and
+    each class of a step runs as one launch of a captured graph (f12_batch:
+    concurrent branches, tuned persistent contraction grids).  The plain path
+    (per-shape launches on one stream, as the default workload runs) is timed
+    on the same quartets."""
+    import torch
+    from paper_1412_5070_amd import f12int
+    from synth import FACTOR_SETS, config_batching_extra, config_plain
+
+    t_start = time.perf_counter()
+
+    def log(msg):
+        print("[bench %7.1fs] %s" % (time.perf_counter() - t_start, msg), file=sys.stderr, flush=True)
+
+    P1 = FACTOR_SETS["P1"]
+    (_, s10), (_, s35) = config_batching_extra()
+    mols = [("20 atoms", config_plain()[1]), ("10 atoms", s10), ("35 atoms", s35)]
+    classes = [int(c) for c in args.classes.split(",")]
+    S = args.slices
+    stream = torch.cuda.current_stream()
+    tune_file = args.tune_file or os.path.join("/tmp", "f12_batch_tune_%d.txt" % os.getpid())
+    geo = []
+    for name, sh in mols:
+        basis = f12int.Basis.from_shells(sh)
+        geo.append((name, basis, f12int.Pairs(basis, 0)))
+    steps_total = args.warmup + args.steps
+    work = []
+    for cls in classes:
+        kern = f12int.Kernel(cls, P1, P1)
+        kscr = f12int.Kernel(3, P1, P1) if cls == 5 else kern
+        lists = []
+        for (name, basis, pairs) in geo:
+            Q = f12int.Quartets.build_device(pairs, pairs, cls, screen_tol=1e-12, screen_kernel=kscr)
+            offs = Q.offsets()
+            lists.append((Q, offs, name))
+            log("I%d %s: %d quartets kept by the screen" % (cls, name, Q.n_quartets))
+        work.append({"cls": cls, "kern": kern, "kscr": kscr, "lists": lists})
+
+    ls_of = {}
+    for wk in work:
+        for (Q, offs, name) in wk["lists"]:
+            ls_of[id(Q)] = Q.groups()[0]
+
+    def step_parts(wk, step, ring):
+        parts, pos = [], 0
+        for (Q, offs, name) in wk["lists"]:
+            starts = ls_of[id(Q)]
+            for g in range(len(starts) - 1):
+                a, b = int(starts[g]), int(starts[g + 1])
+                n = b - a
+                sl = (step + g) % S
+                s0, s1 = a + (n * sl) // S, a + (n * (sl + 1)) // S
+                if s1 <= s0:
+                    continue
+                size = int(offs[s1] - offs[s0])
+                parts.append((Q, s0, s1, ring[pos:pos + size]))
+                pos += size
+        assert pos <= ring.numel()
+        return parts
+
+    # output buffer per class: the largest step of that class
+    for wk in work:
+        need = 0
+        for step in range(steps_total):
+            tot = 0
+            for (Q, offs, name) in wk["lists"]:
+                starts = ls_of[id(Q)]
+                for g in range(len(starts) - 1):
+                    a, b = int(starts[g]), int(starts[g + 1])
+                    sl = (step + g) % S
+                    s0, s1 = a + ((b - a) * sl) // S, a + ((b - a) * (sl + 1)) // S
+                    tot += int(offs[s1] - offs[s0])
+            need = max(need, tot)
+        wk["ring"] = torch.empty(max(need, 1), dtype=torch.float64, device="cuda")
+        wk["batches"] = []
+        for step in range(steps_total):
+            parts = step_parts(wk, step, wk["ring"])
+            t0 = time.perf_counter()
+            bt = f12int.Batch(parts, wk["kern"], nbranch=args.branches, tune=True, tune_path=tune_file)
+            wk["batches"].append((bt, parts))
+            log("I%d step %d: batch of %d quartets, %d parts, %d chunks (%.1f s to build)"
+                % (wk["cls"], step, bt.n_quartets, len(parts), bt.n_chunks, time.perf_counter() - t0))
+
+    def run(step, batched, rec):
+        for wk in work:
+            bt, parts = wk["batches"][step]
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            if batched:
+                bt.launch(stream)
+            else:
+                for (Q, s0, s1, out) in parts:
+                    f12int.eval_into(Q, wk["kern"], out, s0, s1, stream)
+            e1.record(stream)
+            if rec is not None:
+                rec.append((wk["cls"], bt.n_quartets, e0, e1))
+        torch.cuda.synchronize()
+
+    res = {}
+    for mode in ("batched", "plain"):
+        for w in range(args.warmup):
+            run(w, mode == "batched", None)
+        f12int.stream_status()
+        rec = []
+        t0 = time.perf_counter()
+        for s_ in range(args.steps):
+            run(args.warmup + s_, mode == "batched", rec)
+            log("%s step %d done" % (mode, s_))
+        elapsed = time.perf_counter() - t0
+        f12int.stream_status()
+        nq = sum(n for (_, n, _, _) in rec)
+        per = {}
+        for (cls, n, e0, e1) in rec:
+            d = per.setdefault("I%d" % cls, [0, 0.0])
+            d[0] += n
+            d[1] += e0.elapsed_time(e1) / 1e3
+        res[mode] = {"value": nq / elapsed, "elapsed": elapsed, "nq": nq,
+                     "per_class": {k: v[0] / v[1] for k, v in per.items()}}
+    grids = {}
+    wk0 = work[0]
+    for lab in range(7):
+        for lcd in range(7):
+            for i5 in (0, 1):
+                for wk in work:
+                    try:
+                        grids["%d_%d_%s" % (lab, lcd, "I5" if i5 else "")] = wk["batches"][0][0].grid(lab, lcd, i5)
+                        break
+                    except f12int.F12Error:
+                        pass
+    line = {
+        "metric": METRIC,
+        "value": res["batched"]["value"],
+        "unit": "quartets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["batched"]["elapsed"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "batching: the 20-atom (seed 5070), 10-atom (seed 5071) and 35-atom (seed 5072) "
+                        "molecules, s,s,p,p,d,f shells with 1-6 primitives, every unique quartet kept by "
+                        "the 1e-12 screen, I2-I6 (factor P1); each step takes 1/%d of every shape group "
+                        "of every list and runs each class as one captured graph (%d branches, tuned "
+                        "persistent grids)" % (S, args.branches),
+            "classes": ["I%d" % c for c in classes],
+            "quartets_in_lists": {"I%d" % wk["cls"]: {name: Q.n_quartets for (Q, _, name) in wk["lists"]}
+                                  for wk in work},
+            "quartets_per_step": res["batched"]["nq"] // max(args.steps, 1),
+        },
+        "per_class_quartets_per_s": res["batched"]["per_class"],
+        "plain_path_same_quartets": {"value": res["plain"]["value"], "per_class": res["plain"]["per_class"]},
+        "speedup_vs_plain": res["batched"]["value"] / res["plain"]["value"],
+        "tuned_contraction_grids": grids,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,6 +532,12 @@ def main():
     ap.add_argument("--pipeline", action="store_true",
                     help="run the next slice's radial derivatives on a second stream while the current "
                          "slice contracts (launch timings then overlap)")
+    ap.add_argument("--workload", choices=("plain", "batched"), default="plain",
+                    help="plain: the 20-atom molecule through per-shape launches (default); batched: the "
+                         "20-, 10- and 35-atom molecules, each class in one captured graph per step")
+    ap.add_argument("--slices", type=int, default=64, help="batched: steps that cover the whole job")
+    ap.add_argument("--branches", type=int, default=4, help="batched: concurrent branches of each graph")
+    ap.add_argument("--tune-file", default=None, help="batched: tuning results to read and update")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (three times) and exit: "
                          "the reference reading that scales the HBM byte counters")
@@ -375,6 +548,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.workload == "batched":
+        batched_main(args)
         return
 
     import torch

@@ -83,6 +83,7 @@ typedef struct f12_basis f12_basis;
 typedef struct f12_pairs f12_pairs;
 typedef struct f12_kernel f12_kernel;
 typedef struct f12_quartets f12_quartets;
+typedef struct f12_batch f12_batch;
 
 /* ---------------------------------------------------------------- basis ---- */
 /* Copies the geometry and shells.  xyz: ncenter*3 doubles; shells: nshell
@@ -139,6 +140,18 @@ void f12_kernel_destroy(f12_kernel *k);
 int f12_quartets_build(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
                        double screen_tol, const f12_kernel *screen_kernel, void *stream,
                        f12_quartets **out, int64_t *n_quartets, int64_t *n_out_doubles);
+/* The same list as f12_quartets_build (same arguments, same quartets in the
+ * same public order), built on the device: candidate quartets are generated
+ * from their enumeration index, screened with the same estimate (per-pair
+ * factors from the host, the per-quartet growth term on the device, so a
+ * quartet whose estimate lies within rounding of screen_tol may be decided
+ * the other way), compacted, and ordered by a stable radix sort on
+ * (l_a, l_b, l_c, l_d) and decreasing primitive count; offsets by prefix
+ * sums.  The call returns when the list is complete.  Memory: about 64 bytes
+ * of device memory per kept quartet during the build. */
+int f12_quartets_build_device(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
+                              double screen_tol, const f12_kernel *screen_kernel, void *stream,
+                              f12_quartets **out, int64_t *n_quartets, int64_t *n_out_doubles);
 /* An explicit list of nq shell quadruples (a, b, c, d) (host int32[4*nq]);
  * bra and ket must be ordered pair sets.  The public order groups the list
  * by (l_a, l_b, l_c, l_d) and by decreasing primitive count inside a group
@@ -151,6 +164,12 @@ int f12_quartets_from_list(const f12_pairs *bra, const f12_pairs *ket, int32_t c
 int f12_quartet_offsets(const f12_quartets *q, int64_t *offsets);
 /* shell_quads: host int32[4 * n_quartets] in public order. */
 int f12_quartet_list(const f12_quartets *q, int32_t *shell_quads);
+/* Shape groups of the public order: group g holds quartets
+ * [starts[g], starts[g+1]) of angular momenta ls[4g .. 4g+3] = (l_a, l_b,
+ * l_c, l_d).  *ngroups receives the number of groups; up to cap groups are
+ * written (starts: host int64[cap + 1], ls: host int32[4 cap]; either may be
+ * NULL to query the count). */
+int f12_quartet_groups(const f12_quartets *q, int32_t *ngroups, int64_t *starts, int32_t *ls, int32_t cap);
 /* Number of primitive quartets in the list (work measure). */
 int f12_quartets_prim_count(const f12_quartets *q, int64_t *n_prim_quartets);
 void f12_quartets_destroy(f12_quartets *q);
@@ -196,6 +215,40 @@ int f12_eval_stage(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_
                    double *d_out, int64_t out_capacity, int32_t stage, void *stream);
 /* Primitive quartets the list's scratch holds (bound for f12_eval_stage). */
 int f12_quartets_scratch_prims(const f12_quartets *q, int64_t *n_prim_quartets);
+
+/* -------------------------------------------------------------- batches ---- */
+/* One class's quartets of every (l_a l_b|l_c l_d) shape, from nlists quartet
+ * lists (ranges [q_begin[i], q_end[i]) of list i, written to d_outs[i] as
+ * f12_eval writes them: block q at d_outs[i] + offsets[q] - offsets[q_begin[i]]),
+ * evaluated by one launch of a captured HIP graph (the E.R.E route of
+ * Eq. (ii) with A_n of Eq. (bfinal), as f12_eval computes it; results are
+ * identical).  The graph forks into nbranch (1..16) concurrent branches, each
+ * with its own radial-derivative scratch (2^21 primitive quartets x 15
+ * doubles, 252 MiB) and a chain of chunks; chunks are dealt longest-first to
+ * the least-loaded branch.  Contraction launches run persistent grids of G
+ * work-groups where that is faster: with tune = 1 the contraction of one
+ * sample chunk per shape is timed for G in {one work-group per quartet, 256,
+ * 512, 1024, 2048, 4096} (this writes that chunk's output range once, which
+ * the graph rewrites); with tune = 0 every shape uses one work-group per
+ * quartet.  tune_path (may be NULL): a text file of "L_ab L_cd i5 G" lines
+ * read first (shapes found there are not timed) and rewritten with what was
+ * learned.  The lists, the kernel and the outputs must outlive the batch.
+ * Synchronous (uses `stream` for the tuning and set-up).  Errors: F12_EINVAL
+ * (arguments, class mismatch, unwritable tune_path), F12_EBUFSIZE (an output
+ * capacity too small), F12_ENOMEM, F12_EDEVICE. */
+int f12_batch_create(int32_t nlists, f12_quartets *const *lists, const int64_t *q_begin,
+                     const int64_t *q_end, const f12_kernel *k, double *const *d_outs,
+                     const int64_t *out_caps, int32_t nbranch, int32_t tune, const char *tune_path,
+                     void *stream, f12_batch **out);
+/* Enqueues one replay of the batch's graph on `stream` (asynchronous).  A
+ * batch's replays share its scratch: do not overlap two replays of one batch. */
+int f12_batch_launch(f12_batch *b, void *stream);
+/* Quartets, primitive quartets and chunks of the batch. */
+int f12_batch_info(const f12_batch *b, int64_t *n_quartets, int64_t *n_prim_quartets, int64_t *n_chunks);
+/* The contraction grid chosen for shape (L_ab, L_cd, i5): 0 = one work-group
+ * per quartet, G > 0 = persistent; F12_EINVAL if the batch has no such shape. */
+int f12_batch_grid(const f12_batch *b, int32_t lab, int32_t lcd, int32_t i5, int64_t *grid);
+void f12_batch_destroy(f12_batch *b);
 
 /* ------------------------------------------------------------ diagnostics -- */
 /* Radial derivatives A_n = (R^-1 d/dR)^n B_i (Eq. (bfinal), n = 0..L) of the

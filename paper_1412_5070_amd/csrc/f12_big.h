@@ -299,7 +299,11 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
     }
   }
 
-  const int64_t q = a.qa + blockIdx.x;
+  // one contracted quartet per pass; a grid smaller than the range makes the
+  // work-groups persistent (quartet blockIdx.x, then + gridDim.x, ...), and the
+  // set-up above is paid once per work-group
+  for (int64_t qi = blockIdx.x; qi < a.nqc; qi += gridDim.x) {
+  const int64_t q = a.qa + qi;
   const int64_t bp = a.qb[q], kp = a.qk[q];
   const PairsDev &bra = a.bra, &ket = a.ket;
   const int nbra = bra.ka[bp] * bra.kb[bp];
@@ -606,6 +610,8 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
   }
   __syncthreads();
   hrr_store(Uf, la, lb, lc, ld, nf, CD, a.out + o, tid, NT);
+  __syncthreads();  // Uf is rewritten by the next quartet
+  }
 }
 
 // Ket primitives per pass: more when the shape's LDS is small, so that
@@ -630,6 +636,7 @@ inline int launch_big_t(const ContractArgs &a, unsigned nblocks, hipStream_t st)
       return -1;
     attr = true;
   }
+  if (nblocks == 0) return 0;  // set-up only (before a graph capture)
   hipLaunchKernelGGL((big_kernel<LAB, LCD, MODE, NJ>), dim3(nblocks), dim3(256), S::BYTES, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

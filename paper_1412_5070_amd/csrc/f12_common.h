@@ -122,7 +122,7 @@ __device__ inline void e_tables_wg(double a, double b, double ABx, double ABy, d
 struct ContractArgs {
   PairsDev bra, ket;
   const int64_t *qb, *qk, *qoff, *qprim;
-  int64_t qa, p0, np;
+  int64_t qa, nqc, p0, np;  // quartets [qa, qa + nqc)
   const double *A;
   int la, lb, lc, ld, i5;
   double *out;

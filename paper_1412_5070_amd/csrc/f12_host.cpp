@@ -15,131 +15,12 @@
 #include "../../include/f12int.h"
 #include "f12_dd.h"
 #include "f12_internal.h"
+#include "f12_k2.h"
 #include "f12_launch.h"
 
 using namespace f12;
 
-// ============================================================================
-// helpers
-// ============================================================================
-namespace {
-
-template <typename T>
-struct DevBuf {
-  T *ptr = nullptr;
-  size_t n = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf &) = delete;
-  DevBuf &operator=(const DevBuf &) = delete;
-  ~DevBuf() { release(); }
-  void release() {
-    if (ptr) (void)hipFree(ptr);
-    ptr = nullptr;
-    n = 0;
-  }
-  bool alloc(size_t count) {
-    release();
-    if (count == 0) count = 1;
-    if (hipMalloc((void **)&ptr, count * sizeof(T)) != hipSuccess) {
-      ptr = nullptr;
-      return false;
-    }
-    n = count;
-    return true;
-  }
-  bool upload(const std::vector<T> &v) {
-    if (!alloc(v.size())) return false;
-    if (v.empty()) return true;
-    return hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
-  }
-};
-
-inline int ncart(int l) { return (l + 1) * (l + 2) / 2; }
-
-}  // namespace
-
-// ============================================================================
-// opaque handles
-// ============================================================================
-struct f12_basis {
-  int32_t ncenter = 0, nshell = 0, nprim = 0;
-  std::vector<double> xyz, exps, coefs;
-  std::vector<f12_shell> shells;
-};
-
-struct f12_pairs {
-  int32_t ordered = 0, nshell = 0;
-  int64_t nsp = 0, npp = 0;
-  // host copies used for enumeration
-  std::vector<int32_t> sa, sb, la, lb, ka, kb;
-  std::vector<int64_t> pp_off;
-  // per shell pair, for the screening estimate: midpoint of A and B, |A - B|,
-  // smallest exponent sum a + b and largest exponent over the primitive pairs
-  std::vector<double> midx, midy, midz, ablen, pmin, emax;
-  DevBuf<int32_t> d_sa, d_sb, d_la, d_lb, d_ka, d_kb;
-  DevBuf<int64_t> d_pp_off;
-  DevBuf<double> d_ABx, d_ABy, d_ABz;
-  DevBuf<double> d_ea, d_eb, d_p, d_Px, d_Py, d_Pz, d_cab;
-  PairsDev dev() const {
-    PairsDev d;
-    d.nsp = nsp;
-    d.npp = npp;
-    d.nshell = nshell;
-    d.ordered = ordered;
-    d.sa = d_sa.ptr;
-    d.sb = d_sb.ptr;
-    d.la = d_la.ptr;
-    d.lb = d_lb.ptr;
-    d.ka = d_ka.ptr;
-    d.kb = d_kb.ptr;
-    d.pp_off = d_pp_off.ptr;
-    d.ABx = d_ABx.ptr;
-    d.ABy = d_ABy.ptr;
-    d.ABz = d_ABz.ptr;
-    d.ea = d_ea.ptr;
-    d.eb = d_eb.ptr;
-    d.p = d_p.ptr;
-    d.Px = d_Px.ptr;
-    d.Py = d_Py.ptr;
-    d.Pz = d_Pz.ptr;
-    d.cab = d_cab.ptr;
-    return d;
-  }
-};
-
-struct HostTerm {
-  double c, alpha, b, g;
-};
-
-struct f12_kernel {
-  int32_t cls = 0;
-  std::vector<HostTerm> terms;
-  KernelDev host_desc;  // with device pointers filled in
-  DevBuf<KernelDev> d_desc;
-  std::vector<std::unique_ptr<DevBuf<double>>> tables;
-  DevBuf<double> d_phi;
-  int maxL = LTOT_MAX;
-};
-
-struct Bin {
-  int la, lb, lc, ld;
-  int64_t q0, nq;
-};
-
-struct f12_quartets {
-  const f12_pairs *bra = nullptr, *ket = nullptr;
-  int32_t cls = 0;
-  int64_t nq = 0, nout = 0, nprim = 0;
-  std::vector<int64_t> qb, qk, qoff, qprim;  // processing (= public) order
-  std::vector<Bin> bins;
-  DevBuf<int64_t> d_qb, d_qk, d_qoff, d_qprim;
-  DevBuf<double> d_A;
-  int64_t a_cap_prims = 0;
-  int64_t max_qprim = 0;  // largest primitive-quartet count of one quartet
-  // range whose radial derivatives sit in d_A after f12_eval_stage(stage 1)
-  int64_t stage_qa = -1, stage_qe = -1;
-  const f12_kernel *stage_k = nullptr;
-};
+#include "f12_handles.h"
 
 // ============================================================================
 // error strings
@@ -827,8 +708,8 @@ int finish_quartets(f12_quartets *Q, std::vector<int64_t> &qb, std::vector<int64
   Q->qprim.assign(nq + 1, 0);
   for (int64_t i = 0; i < nq; ++i) {
     const int64_t b = Q->qb[i], k = Q->qk[i];
-    Q->qoff[i + 1] = Q->qoff[i] + (int64_t)ncart(B->la[b]) * ncart(B->lb[b]) * ncart(K->la[k]) *
-                                      ncart(K->lb[k]);
+    Q->qoff[i + 1] = Q->qoff[i] + (int64_t)ncart_host(B->la[b]) * ncart_host(B->lb[b]) * ncart_host(K->la[k]) *
+                                      ncart_host(K->lb[k]);
     Q->qprim[i + 1] =
         Q->qprim[i] + (int64_t)B->ka[b] * B->kb[b] * (int64_t)K->ka[k] * K->kb[k];
   }
@@ -879,53 +760,110 @@ extern "C" int f12_quartets_from_list(const f12_pairs *bra, const f12_pairs *ket
   return F12_OK;
 }
 
-extern "C" int f12_quartets_build(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
-                                  double screen_tol, const f12_kernel *screen_kernel, void *stream,
-                                  f12_quartets **out, int64_t *n_quartets,
-                                  int64_t *n_out_doubles) {
+namespace {
+
+// Screening estimate of f12_quartets_build.  Q_ab Q_cd alone bounds
+// |(ab|k|cd)| only for a positive-definite kernel; the long-range part
+// c0 r^rho e^{B r} of Eq. (rs12) grows with r, so the estimate carries the
+// growth of the kernel's undamped terms (g = 0, b > 0),
+//   kappa(r) = sum |c_t| r^(alpha_t - 1) e^(b_t r),
+// from r = 1 to the largest distance R_eff between the primitive-pair
+// centres of the two pairs (each P lies on its segment AB), and per pair the
+// growth of e^{b |r - P|} over the pair density's extent,
+//   exp(b sqrt((l_a + l_b + 1) / (2 p_min)) + b^2 / (4 p_min)).
+// I5 = 1/2 (lap_A - lap_B) I3 (Eq. (I5_)) multiplies the bra by up to about
+// the largest bra exponent times (2 l + 3).
+struct ScreenEst {
+  std::vector<double> Sb, Sk;  // Q times the pair's extent factor
+  std::vector<HostTerm> grow;
+  double kappa1 = 1.0;
+  double kappa(double r) const {
+    double v = 0.0;
+    for (const HostTerm &t : grow) v += std::fabs(t.c) * std::pow(r, t.alpha - 1.0) * std::exp(t.b * r);
+    return v;
+  }
+};
+
+int screen_estimate(const f12_pairs *bra, const f12_pairs *ket, int32_t cls, const f12_kernel *screen_kernel,
+                    hipStream_t st, ScreenEst &E) {
+  std::vector<double> Qb, Qk;
+  // Q_ab = sqrt(max |(ab|k|ab)|) over the diagonal quartets of the pair set
+  auto diag = [&](const f12_pairs *P, std::vector<double> &Qv) -> int {
+    std::unique_ptr<f12_quartets> D(new (std::nothrow) f12_quartets);
+    if (!D) return F12_ENOMEM;
+    D->bra = P;
+    D->ket = P;
+    D->cls = screen_kernel->cls == 5 ? 3 : screen_kernel->cls;
+    std::vector<int64_t> qb(P->nsp), qk(P->nsp);
+    for (int64_t i = 0; i < P->nsp; ++i) qb[i] = qk[i] = i;
+    int s = finish_quartets(D.get(), qb, qk);
+    if (s) return s;
+    DevBuf<double> dout;
+    if (!dout.alloc(D->nout)) return F12_ENOMEM;
+    s = eval_range(D.get(), screen_kernel, 0, D->nq, dout.ptr, D->d_A.ptr, D->a_cap_prims, st);
+    if (s) return s;
+    std::vector<double> h(D->nout);
+    if (hipMemcpyAsync(h.data(), dout.ptr, D->nout * sizeof(double), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return F12_EDEVICE;
+    Qv.assign(P->nsp, 0.0);
+    for (int64_t i = 0; i < D->nq; ++i) {
+      double m = 0;
+      for (int64_t o = D->qoff[i]; o < D->qoff[i + 1]; ++o) m = std::max(m, std::fabs(h[o]));
+      Qv[D->qb[i]] = std::sqrt(m);
+    }
+    return F12_OK;
+  };
+  int s = diag(bra, Qb);
+  if (s) return s;
+  if (ket == bra)
+    Qk = Qb;
+  else if ((s = diag(ket, Qk)))
+    return s;
+  double bmax = 0.0;
+  E.grow.clear();
+  for (const HostTerm &t : screen_kernel->terms)
+    if (t.g == 0.0 && t.b > 0.0) {
+      E.grow.push_back(t);
+      bmax = std::max(bmax, t.b);
+    }
+  if ((int)E.grow.size() > K2_MAX_GROW) return F12_EPARAM;
+  E.kappa1 = E.grow.empty() ? 1.0 : E.kappa(1.0);
+  auto pair_factor = [&](const f12_pairs *P, int64_t i, bool i5bra) {
+    const double pm = P->pmin[i];
+    double f = std::exp(bmax * std::sqrt((P->la[i] + P->lb[i] + 1) / (2.0 * pm)) + bmax * bmax / (4.0 * pm));
+    if (i5bra) f *= P->emax[i] * (2 * std::max(P->la[i], P->lb[i]) + 3);
+    return f;
+  };
+  E.Sb.resize(bra->nsp);
+  E.Sk.resize(ket->nsp);
+  for (int64_t b = 0; b < bra->nsp; ++b) E.Sb[b] = Qb[b] * pair_factor(bra, b, cls == 5);
+  for (int64_t k = 0; k < ket->nsp; ++k) E.Sk[k] = Qk[k] * pair_factor(ket, k, false);
+  return F12_OK;
+}
+
+int check_build_args(const f12_pairs *bra, const f12_pairs *ket, int32_t cls, double screen_tol,
+                     const f12_kernel *screen_kernel, f12_quartets **out) {
   if (!bra || !ket || !out || cls < 1 || cls > 6) return F12_EINVAL;
   *out = nullptr;
   if (bra->ordered || ket->ordered) return F12_EINVAL;  // unordered pair sets
   if (bra->nshell != ket->nshell) return F12_EINVAL;
   if (screen_tol > 0 && !screen_kernel) return F12_EINVAL;
-  std::vector<double> Qb, Qk;
+  return F12_OK;
+}
+
+}  // namespace
+
+extern "C" int f12_quartets_build(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
+                                  double screen_tol, const f12_kernel *screen_kernel, void *stream,
+                                  f12_quartets **out, int64_t *n_quartets,
+                                  int64_t *n_out_doubles) {
+  int s = check_build_args(bra, ket, cls, screen_tol, screen_kernel, out);
+  if (s) return s;
   hipStream_t st = (hipStream_t)stream;
-  if (screen_tol > 0) {
-    // Q_ab = sqrt(max |(ab|k|ab)|) over the diagonal quartets of the pair set
-    auto diag = [&](const f12_pairs *P, std::vector<double> &Qv) -> int {
-      std::unique_ptr<f12_quartets> D(new (std::nothrow) f12_quartets);
-      if (!D) return F12_ENOMEM;
-      D->bra = P;
-      D->ket = P;
-      D->cls = screen_kernel->cls == 5 ? 3 : screen_kernel->cls;
-      std::vector<int64_t> qb(P->nsp), qk(P->nsp);
-      for (int64_t i = 0; i < P->nsp; ++i) qb[i] = qk[i] = i;
-      int s = finish_quartets(D.get(), qb, qk);
-      if (s) return s;
-      DevBuf<double> dout;
-      if (!dout.alloc(D->nout)) return F12_ENOMEM;
-      s = eval_range(D.get(), screen_kernel, 0, D->nq, dout.ptr, D->d_A.ptr, D->a_cap_prims, st);
-      if (s) return s;
-      std::vector<double> h(D->nout);
-      if (hipMemcpyAsync(h.data(), dout.ptr, D->nout * sizeof(double), hipMemcpyDeviceToHost,
-                         st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess)
-        return F12_EDEVICE;
-      Qv.assign(P->nsp, 0.0);
-      for (int64_t i = 0; i < D->nq; ++i) {
-        double m = 0;
-        for (int64_t o = D->qoff[i]; o < D->qoff[i + 1]; ++o) m = std::max(m, std::fabs(h[o]));
-        Qv[D->qb[i]] = std::sqrt(m);
-      }
-      return F12_OK;
-    };
-    int s = diag(bra, Qb);
-    if (s) return s;
-    if (ket == bra)
-      Qk = Qb;
-    else if ((s = diag(ket, Qk)))
-      return s;
-  }
+  ScreenEst E;
+  if (screen_tol > 0 && (s = screen_estimate(bra, ket, cls, screen_kernel, st, E))) return s;
   std::unique_ptr<f12_quartets> Q(new (std::nothrow) f12_quartets);
   if (!Q) return F12_ENOMEM;
   Q->bra = bra;
@@ -933,54 +871,19 @@ extern "C" int f12_quartets_build(const f12_pairs *bra, const f12_pairs *ket, in
   Q->cls = cls;
   std::vector<int64_t> qb, qk;
   const bool fold = (cls != 5);  // I5 has no bra-ket symmetry
-  // Screening estimate.  Q_ab Q_cd alone bounds |(ab|k|cd)| only for a
-  // positive-definite kernel; the long-range part c0 r^rho e^{B r} of
-  // Eq. (rs12) grows with r, so the estimate carries the growth of the
-  // kernel's undamped terms (g = 0, b > 0),
-  //   kappa(r) = sum |c_t| r^(alpha_t - 1) e^(b_t r),
-  // from r = 1 to the largest distance R_eff between the primitive-pair
-  // centres of the two pairs (each P lies on its segment AB), and per pair
-  // the growth of e^{b |r - P|} over the pair density's extent,
-  //   exp(b sqrt((l_a + l_b + 1) / (2 p_min)) + b^2 / (4 p_min)).
-  // I5 = 1/2 (lap_A - lap_B) I3 (Eq. (I5_)) multiplies the bra by up to about
-  // the largest bra exponent times (2 l + 3).
-  std::vector<HostTerm> grow;
-  double bmax = 0.0;
-  if (screen_tol > 0)
-    for (const HostTerm &t : screen_kernel->terms)
-      if (t.g == 0.0 && t.b > 0.0) {
-        grow.push_back(t);
-        bmax = std::max(bmax, t.b);
-      }
-  auto kappa = [&](double r) {
-    double v = 0.0;
-    for (const HostTerm &t : grow) v += std::fabs(t.c) * std::pow(r, t.alpha - 1.0) * std::exp(t.b * r);
-    return v;
-  };
-  const double kappa1 = grow.empty() ? 1.0 : kappa(1.0);
-  auto pair_factor = [&](const f12_pairs *P, int64_t i, bool i5bra) {
-    const double pm = P->pmin[i];
-    double f = std::exp(bmax * std::sqrt((P->la[i] + P->lb[i] + 1) / (2.0 * pm)) + bmax * bmax / (4.0 * pm));
-    if (i5bra) f *= P->emax[i] * (2 * std::max(P->la[i], P->lb[i]) + 3);
-    return f;
-  };
-  std::vector<double> Sb, Sk;
-  if (screen_tol > 0) {
-    Sb.resize(bra->nsp);
-    Sk.resize(ket->nsp);
-    for (int64_t b = 0; b < bra->nsp; ++b) Sb[b] = Qb[b] * pair_factor(bra, b, cls == 5);
-    for (int64_t k = 0; k < ket->nsp; ++k) Sk[k] = Qk[k] * pair_factor(ket, k, false);
-  }
   for (int64_t b = 0; b < bra->nsp; ++b) {
     int64_t kmax = fold ? std::min(b, ket->nsp - 1) : ket->nsp - 1;
     for (int64_t k = 0; k <= kmax; ++k) {
       if (screen_tol > 0) {
-        double est = Sb[b] * Sk[k];
-        if (est < screen_tol && !grow.empty()) {
+        double est = E.Sb[b] * E.Sk[k];
+        if (est < screen_tol && !E.grow.empty()) {
           const double dx = bra->midx[b] - ket->midx[k], dy = bra->midy[b] - ket->midy[k],
                        dz = bra->midz[b] - ket->midz[k];
           const double reff = std::sqrt(dx * dx + dy * dy + dz * dz) + 0.5 * (bra->ablen[b] + ket->ablen[k]);
-          if (reff > 1.0) est *= std::max(1.0, kappa(reff) / kappa1);
+          if (reff > 1.0) {
+            const double g = E.kappa(reff) / E.kappa1;
+            if (g > 1.0) est *= g;
+          }
         }
         if (est < screen_tol) continue;
       }
@@ -988,8 +891,126 @@ extern "C" int f12_quartets_build(const f12_pairs *bra, const f12_pairs *ket, in
       qk.push_back(k);
     }
   }
-  int s = finish_quartets(Q.get(), qb, qk);
+  s = finish_quartets(Q.get(), qb, qk);
   if (s) return s;
+  if (n_quartets) *n_quartets = Q->nq;
+  if (n_out_doubles) *n_out_doubles = Q->nout;
+  *out = Q.release();
+  return F12_OK;
+}
+
+extern "C" int f12_quartets_build_device(const f12_pairs *bra, const f12_pairs *ket, int32_t cls,
+                                         double screen_tol, const f12_kernel *screen_kernel, void *stream,
+                                         f12_quartets **out, int64_t *n_quartets, int64_t *n_out_doubles) {
+  int s = check_build_args(bra, ket, cls, screen_tol, screen_kernel, out);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  ScreenEst E;
+  if (screen_tol > 0 && (s = screen_estimate(bra, ket, cls, screen_kernel, st, E))) return s;
+  const bool fold = (cls != 5);
+  if (fold && bra->nsp != ket->nsp) return F12_EINVAL;
+  // per-pair tables on the device
+  auto pair_tables = [&](const f12_pairs *P, const std::vector<double> &S, DevBuf<double> &dS,
+                         DevBuf<double> &dmid, DevBuf<double> &dab, DevBuf<int32_t> &dcls,
+                         DevBuf<int32_t> &dnp, DevBuf<int32_t> &dnc) -> bool {
+    std::vector<double> mid(3 * P->nsp);
+    std::vector<int32_t> c(P->nsp), np(P->nsp), nc(P->nsp);
+    for (int64_t i = 0; i < P->nsp; ++i) {
+      mid[3 * i] = P->midx[i];
+      mid[3 * i + 1] = P->midy[i];
+      mid[3 * i + 2] = P->midz[i];
+      c[i] = P->la[i] * (LMAX + 1) + P->lb[i];
+      np[i] = P->ka[i] * P->kb[i];
+      nc[i] = ncart_host(P->la[i]) * ncart_host(P->lb[i]);
+    }
+    std::vector<double> Sv = S.empty() ? std::vector<double>(P->nsp, 0.0) : S;
+    return dS.upload(Sv) && dmid.upload(mid) && dab.upload(P->ablen) && dcls.upload(c) && dnp.upload(np) &&
+           dnc.upload(nc);
+  };
+  DevBuf<double> bS, bmid, bab, kS, kmid, kab;
+  DevBuf<int32_t> bcls, bnp, bnc, kcls, knp, knc;
+  if (!pair_tables(bra, E.Sb, bS, bmid, bab, bcls, bnp, bnc) ||
+      !pair_tables(ket, E.Sk, kS, kmid, kab, kcls, knp, knc))
+    return F12_ENOMEM;
+  K2Params P;
+  std::memset(&P, 0, sizeof(P));
+  P.nb = bra->nsp;
+  P.nk = ket->nsp;
+  P.fold = fold;
+  P.tol = screen_tol;
+  P.Sb = bS.ptr;
+  P.Sk = kS.ptr;
+  P.bmid = bmid.ptr;
+  P.kmid = kmid.ptr;
+  P.bab = bab.ptr;
+  P.kab = kab.ptr;
+  P.bcls = bcls.ptr;
+  P.kcls = kcls.ptr;
+  P.bnp = bnp.ptr;
+  P.knp = knp.ptr;
+  P.bnc = bnc.ptr;
+  P.knc = knc.ptr;
+  P.ngrow = screen_tol > 0 ? (int)E.grow.size() : 0;
+  for (int t = 0; t < P.ngrow; ++t) {
+    P.gc[t] = std::fabs(E.grow[t].c);
+    P.ga[t] = E.grow[t].alpha;
+    P.gb[t] = E.grow[t].b;
+  }
+  P.kappa1 = E.kappa1;
+  const uint64_t ncand = fold ? (uint64_t)bra->nsp * (bra->nsp + 1) / 2 : (uint64_t)bra->nsp * ket->nsp;
+  uint64_t *d_idx = nullptr;
+  int64_t n = 0;
+  if (k2_select(P, ncand, &d_idx, &n, st) != 0) return F12_EDEVICE;
+  std::unique_ptr<f12_quartets> Q(new (std::nothrow) f12_quartets);
+  if (!Q) {
+    (void)hipFree(d_idx);
+    return F12_ENOMEM;
+  }
+  Q->bra = bra;
+  Q->ket = ket;
+  Q->cls = cls;
+  constexpr int RAD = LMAX + 1, NBIN = RAD * RAD * RAD * RAD;
+  DevBuf<int64_t> d_start;
+  std::vector<int64_t> start(NBIN, -1);
+  bool ok = Q->d_qb.alloc(n) && Q->d_qk.alloc(n) && Q->d_qoff.alloc(n + 1) && Q->d_qprim.alloc(n + 1) &&
+            d_start.upload(start);
+  if (!ok) {
+    (void)hipFree(d_idx);
+    return F12_ENOMEM;
+  }
+  const int rc = k2_finalize(P, d_idx, n, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qoff.ptr, Q->d_qprim.ptr, d_start.ptr, st);
+  (void)hipFree(d_idx);
+  if (rc != 0) return F12_EDEVICE;
+  // host copies: offsets (chunking, f12_quartet_offsets) and the pair indices
+  Q->qb.resize(n);
+  Q->qk.resize(n);
+  Q->qoff.resize(n + 1);
+  Q->qprim.resize(n + 1);
+  if ((n > 0 && (hipMemcpy(Q->qb.data(), Q->d_qb.ptr, n * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+                 hipMemcpy(Q->qk.data(), Q->d_qk.ptr, n * 8, hipMemcpyDeviceToHost) != hipSuccess)) ||
+      hipMemcpy(Q->qoff.data(), Q->d_qoff.ptr, (n + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(Q->qprim.data(), Q->d_qprim.ptr, (n + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(start.data(), d_start.ptr, NBIN * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return F12_EDEVICE;
+  Q->bins.clear();
+  for (int k = 0; k < NBIN; ++k) {
+    if (start[k] < 0) continue;
+    int64_t e = n;
+    for (int j = k + 1; j < NBIN; ++j)
+      if (start[j] >= 0) {
+        e = start[j];
+        break;
+      }
+    Q->bins.push_back({k / (RAD * RAD * RAD), (k / (RAD * RAD)) % RAD, (k / RAD) % RAD, k % RAD, start[k],
+                       e - start[k]});
+  }
+  Q->nq = n;
+  Q->nout = Q->qoff[n];
+  Q->nprim = Q->qprim[n];
+  Q->max_qprim = 0;
+  for (int64_t i = 0; i < n; ++i) Q->max_qprim = std::max(Q->max_qprim, Q->qprim[i + 1] - Q->qprim[i]);
+  Q->a_cap_prims = std::min<int64_t>(std::max<int64_t>(Q->nprim, 1), (int64_t)1 << 23);
+  if (!Q->d_A.alloc((size_t)Q->a_cap_prims * (LTOT_MAX + 1))) return F12_ENOMEM;
   if (n_quartets) *n_quartets = Q->nq;
   if (n_out_doubles) *n_out_doubles = Q->nout;
   *out = Q.release();
@@ -1009,6 +1030,26 @@ extern "C" int f12_quartet_list(const f12_quartets *q, int32_t *quads) {
     quads[4 * i + 1] = q->bra->sb[q->qb[i]];
     quads[4 * i + 2] = q->ket->sa[q->qk[i]];
     quads[4 * i + 3] = q->ket->sb[q->qk[i]];
+  }
+  return F12_OK;
+}
+
+extern "C" int f12_quartet_groups(const f12_quartets *q, int32_t *ngroups, int64_t *starts, int32_t *ls,
+                                  int32_t cap) {
+  if (!q || !ngroups || cap < 0) return F12_EINVAL;
+  const int n = (int)q->bins.size();
+  *ngroups = n;
+  for (int g = 0; g < n && g < cap; ++g) {
+    if (starts) {
+      starts[g] = q->bins[g].q0;
+      starts[g + 1] = q->bins[g].q0 + q->bins[g].nq;
+    }
+    if (ls) {
+      ls[4 * g] = q->bins[g].la;
+      ls[4 * g + 1] = q->bins[g].lb;
+      ls[4 * g + 2] = q->bins[g].lc;
+      ls[4 * g + 3] = q->bins[g].ld;
+    }
   }
   return F12_OK;
 }

@@ -568,7 +568,7 @@ static int launch_big(int lab, int lcd, int i5, const ContractArgs &a, unsigned 
 int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb, const int64_t *qk,
                     const int64_t *qoff, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
                     int64_t np, const double *A, int la, int lb, int lc, int ld, int i5,
-                    double *out, int64_t out_base, hipStream_t stream) {
+                    double *out, int64_t out_base, hipStream_t stream, int64_t grid) {
   if (nqc <= 0) return 0;
   ContractArgs a;
   a.bra = bra;
@@ -578,6 +578,7 @@ int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
   a.qoff = qoff;
   a.qprim = qprim;
   a.qa = qa;
+  a.nqc = nqc;
   a.p0 = p0;
   a.np = np;
   a.A = A;
@@ -588,7 +589,10 @@ int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
   a.i5 = i5;
   a.out = out;
   a.out_base = out_base;
-  return launch_big(la + lb, lc + ld, i5, a, (unsigned)nqc, stream);
+  // grid > 0: persistent work-groups (at most grid of them); grid == 0: one
+  // work-group per quartet; grid < 0: set the kernel's attributes only
+  const int64_t nb = grid < 0 ? 0 : (grid == 0 ? nqc : (grid < nqc ? grid : nqc));
+  return launch_big(la + lb, lc + ld, i5, a, (unsigned)nb, stream);
 }
 
 // Diagnostic: A_n for explicit (p, q, R) triples (one thread each), R along z.

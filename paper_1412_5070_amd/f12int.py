@@ -47,15 +47,23 @@ EXPORTS = {
     "f12_kernel_terms": (_c_i32, [_vp, _P(_c_i32), _P(_c_dbl), _c_i32]),
     "f12_kernel_destroy": (None, [_vp]),
     "f12_quartets_build": (_c_i32, [_vp, _vp, _c_i32, _c_dbl, _vp, _vp, _P(_vp), _P(_c_i64), _P(_c_i64)]),
+    "f12_quartets_build_device": (_c_i32, [_vp, _vp, _c_i32, _c_dbl, _vp, _vp, _P(_vp), _P(_c_i64), _P(_c_i64)]),
     "f12_quartets_from_list": (_c_i32, [_vp, _vp, _c_i32, _P(_c_i32), _c_i64, _P(_vp), _P(_c_i64)]),
     "f12_quartet_offsets": (_c_i32, [_vp, _P(_c_i64)]),
     "f12_quartet_list": (_c_i32, [_vp, _P(_c_i32)]),
+    "f12_quartet_groups": (_c_i32, [_vp, _P(_c_i32), _P(_c_i64), _P(_c_i32), _c_i32]),
     "f12_quartets_prim_count": (_c_i32, [_vp, _P(_c_i64)]),
     "f12_quartets_destroy": (None, [_vp]),
     "f12_eval": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp]),
     "f12_eval_noalloc": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp]),
     "f12_eval_stage": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i32, _vp]),
     "f12_quartets_scratch_prims": (_c_i32, [_vp, _P(_c_i64)]),
+    "f12_batch_create": (_c_i32, [_c_i32, _P(_vp), _P(_c_i64), _P(_c_i64), _vp, _P(_vp), _P(_c_i64), _c_i32,
+                                  _c_i32, ctypes.c_char_p, _vp, _P(_vp)]),
+    "f12_batch_launch": (_c_i32, [_vp, _vp]),
+    "f12_batch_info": (_c_i32, [_vp, _P(_c_i64), _P(_c_i64), _P(_c_i64)]),
+    "f12_batch_grid": (_c_i32, [_vp, _c_i32, _c_i32, _c_i32, _P(_c_i64)]),
+    "f12_batch_destroy": (None, [_vp]),
     "f12_aux_radial": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _c_i32, _c_i32, _vp, _vp]),
     "f12_aux_w_column": (_c_i32, [_c_dbl, _c_i32, _c_i32, _c_i32, _c_dbl, _P(_c_dbl)]),
     "f12_stream_status": (_c_i32, [_vp]),
@@ -174,6 +182,16 @@ class Quartets:
         return Quartets(h, nq.value, nout.value, bra, ket, cls)
 
     @staticmethod
+    def build_device(bra, ket, cls, screen_tol=0.0, screen_kernel=None, stream=None):
+        """f12_quartets_build_device: the same list, generated, screened and sorted on the GPU."""
+        h, nq, nout = _vp(), _c_i64(), _c_i64()
+        _check(_lib.f12_quartets_build_device(bra.handle, ket.handle, int(cls), float(screen_tol),
+                                              screen_kernel.handle if screen_kernel else None,
+                                              _stream_ptr(stream), ctypes.byref(h), ctypes.byref(nq),
+                                              ctypes.byref(nout)), "f12_quartets_build_device")
+        return Quartets(h, nq.value, nout.value, bra, ket, cls)
+
+    @staticmethod
     def from_list(bra, ket, cls, quads):
         q = np.ascontiguousarray(quads, dtype=np.int32).reshape(-1, 4)
         h, nout = _vp(), _c_i64()
@@ -191,6 +209,18 @@ class Quartets:
         _check(_lib.f12_quartet_list(self.handle, q.ctypes.data_as(_P(_c_i32))), "f12_quartet_list")
         return q
 
+    def groups(self):
+        """Shape groups of the public order: (starts int64[n+1], ls int32[n, 4])."""
+        n = _c_i32()
+        _check(_lib.f12_quartet_groups(self.handle, ctypes.byref(n), None, None, 0), "f12_quartet_groups")
+        starts = np.zeros(n.value + 1, dtype=np.int64)
+        ls = np.zeros((n.value, 4), dtype=np.int32)
+        _check(_lib.f12_quartet_groups(self.handle, ctypes.byref(n), starts.ctypes.data_as(_P(_c_i64)),
+                                       ls.ctypes.data_as(_P(_c_i32)), n.value), "f12_quartet_groups")
+        if n.value == 0:
+            starts[0] = 0
+        return starts, ls
+
     def n_prim(self):
         n = _c_i64()
         _check(_lib.f12_quartets_prim_count(self.handle, ctypes.byref(n)), "f12_quartets_prim_count")
@@ -200,6 +230,45 @@ class Quartets:
         h = getattr(self, "handle", None)
         if h and _lib is not None:
             _lib.f12_quartets_destroy(h)
+        self.handle = None
+
+
+class Batch:
+    """f12_batch_create: one class's quartets from several lists in one captured
+    HIP graph (concurrent branches, tuned persistent contraction grids).
+    parts: list of (Quartets, q_begin, q_end, out tensor)."""
+
+    def __init__(self, parts, kernel, nbranch=4, tune=True, tune_path=None, stream=None):
+        import torch
+        n = len(parts)
+        self.parts, self.kernel = parts, kernel
+        for (_, _, _, out) in parts:
+            assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        lists = (_vp * n)(*[p[0].handle for p in parts])
+        qb = (_c_i64 * n)(*[int(p[1]) for p in parts])
+        qe = (_c_i64 * n)(*[int(p[2]) for p in parts])
+        outs = (_vp * n)(*[_vp(p[3].data_ptr()) for p in parts])
+        caps = (_c_i64 * n)(*[p[3].numel() for p in parts])
+        self.handle = _vp()
+        _check(_lib.f12_batch_create(n, lists, qb, qe, kernel.handle, outs, caps, int(nbranch), int(bool(tune)),
+                                     tune_path.encode() if tune_path else None, _stream_ptr(stream),
+                                     ctypes.byref(self.handle)), "f12_batch_create")
+        a, b, c = _c_i64(), _c_i64(), _c_i64()
+        _check(_lib.f12_batch_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "f12_batch_info")
+        self.n_quartets, self.n_prim, self.n_chunks = a.value, b.value, c.value
+
+    def launch(self, stream=None):
+        _check(_lib.f12_batch_launch(self.handle, _stream_ptr(stream)), "f12_batch_launch")
+
+    def grid(self, lab, lcd, i5):
+        g = _c_i64()
+        _check(_lib.f12_batch_grid(self.handle, int(lab), int(lcd), int(i5), ctypes.byref(g)), "f12_batch_grid")
+        return g.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.f12_batch_destroy(h)
         self.handle = None
 
 
