@@ -517,6 +517,151 @@ def batched_main(args):
     print(json.dumps(line))
 
 
+def precision_main(args):
+    """The precision workload: the 35-atom molecule (seed 5072, 14.4 bohr),
+    every unique quartet kept by the 1e-12 screen, I2-I6 (P1), lists built on
+    the device.  Step s takes slice (s + g) mod --slices of every shape group
+    g; each step is evaluated with the FP64 contraction and with the
+    split-FP32 ket transform (f12_eval_precision) on the same quartets.  The
+    split result is compared with the FP64 one block by block over every
+    evaluated block, and both with the stored oracle values of quartets
+    sampled from the same molecule (tests/golden/prec35.npz)."""
+    import torch
+    from paper_1412_5070_amd import f12int
+    from synth import FACTOR_SETS, config_precision
+
+    t_start = time.perf_counter()
+
+    def log(msg):
+        print("[bench %7.1fs] %s" % (time.perf_counter() - t_start, msg), file=sys.stderr, flush=True)
+
+    P1 = FACTOR_SETS["P1"]
+    _, shells = config_precision()
+    classes = [int(c) for c in args.classes.split(",")]
+    S = args.slices
+    stream = torch.cuda.current_stream()
+    basis = f12int.Basis.from_shells(shells)
+    pairs = f12int.Pairs(basis, 0)
+    gold = {}
+    gpath = os.path.join(ROOT, "tests", "golden", "prec35.npz")
+    if os.path.exists(gpath):
+        with np.load(gpath, allow_pickle=False) as z:
+            gold = {k: z[k] for k in z.files}
+    res, totals = {}, {}
+    for cls in classes:
+        kern = f12int.Kernel(cls, P1, P1)
+        kscr = f12int.Kernel(3, P1, P1) if cls == 5 else kern
+        Q = f12int.Quartets.build_device(pairs, pairs, cls, screen_tol=1e-12, screen_kernel=kscr)
+        offs = Q.offsets()
+        starts, _ = Q.groups()
+        log("I%d: %d quartets kept by the screen" % (cls, Q.n_quartets))
+        steps = []
+        for step in range(args.warmup + args.steps):
+            parts = []
+            for g in range(len(starts) - 1):
+                a, b = int(starts[g]), int(starts[g + 1])
+                sl = (step + g) % S
+                s0, s1 = a + ((b - a) * sl) // S, a + ((b - a) * (sl + 1)) // S
+                if s1 > s0:
+                    parts.append((s0, s1))
+            steps.append(parts)
+        size = max(sum(int(offs[s1] - offs[s0]) for (s0, s1) in parts) for parts in steps)
+        o64 = torch.empty(max(size, 1), dtype=torch.float64, device="cuda")
+        o32 = torch.empty_like(o64)
+        rc = {"fp64": [0, 0.0], "split_fp32": [0, 0.0]}
+        worst_vs64 = 0.0
+        nblocks = 0
+        for step, parts in enumerate(steps):
+            timed = step >= args.warmup
+            for prec, out, key in ((0, o64, "fp64"), (1, o32, "split_fp32")):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                pos = 0
+                for (s0, s1) in parts:
+                    n = int(offs[s1] - offs[s0])
+                    f12int.eval_precision(Q, kern, out[pos:pos + n], prec, s0, s1, stream)
+                    pos += n
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if timed:
+                    rc[key][0] += sum(s1 - s0 for (s0, s1) in parts)
+                    rc[key][1] += e0.elapsed_time(e1) / 1e3
+            if timed:
+                # block-relative error of the split result against FP64, every block of the step
+                lens = np.concatenate([np.diff(offs[s0:s1 + 1]) for (s0, s1) in parts])
+                lt = torch.as_tensor(lens, device="cuda")
+                idx = torch.repeat_interleave(torch.arange(len(lens), device="cuda"), lt)
+                n = int(lens.sum())
+                scale = torch.zeros(len(lens), dtype=torch.float64, device="cuda").scatter_reduce_(
+                    0, idx, o64[:n].abs(), "amax")
+                diff = torch.zeros_like(scale).scatter_reduce_(0, idx, (o32[:n] - o64[:n]).abs(), "amax")
+                ok = scale > 0
+                worst_vs64 = max(worst_vs64, float((diff[ok] / scale[ok]).max()) if bool(ok.any()) else 0.0)
+                nblocks += len(lens)
+            log("I%d step %d done" % (cls, step))
+        # stored oracle sample
+        keys = None
+        worst_or = {"fp64": 0.0, "split_fp32": 0.0}
+        nor, ndrop = 0, 0
+        if gold:
+            quads = Q.quads().astype(np.int64)
+            keys = ((quads[:, 0] * 256 + quads[:, 1]) * 256 + quads[:, 2]) * 256 + quads[:, 3]
+            for name, ref in gold.items():
+                parts_ = name.split("_")
+                if parts_[0] != "c%d" % cls:
+                    continue
+                qd = [int(v) for v in parts_[1:]]
+                hit = np.flatnonzero(keys == ((qd[0] * 256 + qd[1]) * 256 + qd[2]) * 256 + qd[3])
+                if len(hit) == 0:
+                    ndrop += 1
+                    continue
+                i = int(hit[0])
+                for prec, key in ((0, "fp64"), (1, "split_fp32")):
+                    out = torch.empty(int(offs[i + 1] - offs[i]), dtype=torch.float64, device="cuda")
+                    f12int.eval_precision(Q, kern, out, prec, i, i + 1, stream)
+                    got = out.cpu().numpy()
+                    sc = float(np.max(np.abs(ref)))
+                    if cls == 5 and qd[0] == qd[1] and shells[qd[0]].l <= 1:
+                        continue
+                    worst_or[key] = max(worst_or[key], float(np.max(np.abs(got - ref))) / sc)
+                nor += 1
+            del quads, keys
+        f12int.stream_status()
+        res["I%d" % cls] = {
+            "quartets_in_list": Q.n_quartets,
+            "fp64_quartets_per_s": rc["fp64"][0] / rc["fp64"][1],
+            "split_fp32_quartets_per_s": rc["split_fp32"][0] / rc["split_fp32"][1],
+            "split_vs_fp64_max_block_rel_err": worst_vs64, "blocks_compared_with_fp64": nblocks,
+            "vs_stored_oracle": {"blocks": nor, "sampled_blocks_dropped_by_screen": ndrop,
+                                 "fp64_max_block_rel_err": worst_or["fp64"],
+                                 "split_fp32_max_block_rel_err": worst_or["split_fp32"]}}
+        totals[cls] = (rc["split_fp32"][0], rc["split_fp32"][1], rc["fp64"][0], rc["fp64"][1])
+        del Q
+    line = {
+        "metric": METRIC,
+        "value": sum(v[0] for v in totals.values()) / sum(v[1] for v in totals.values()),
+        "unit": "quartets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 + split-f32 ket transform",
+        "data": "synthetic",
+        "config": {"workload": "precision: 35 atoms in a 14.4 bohr cube (seed 5072), s,s,p,p,d,f shells with 1-6 "
+                               "primitives, every unique quartet kept by the 1e-12 screen, I2-I6 (factor P1); "
+                               "each step 1/%d of every shape group, FP64 and split-FP32 contraction on the "
+                               "same quartets" % S},
+        "per_class": res,
+        "fp64_value": sum(v[2] for v in totals.values()) / sum(v[3] for v in totals.values()),
+        "note": "value: split-FP32 quartets/s over all timed steps of all classes; fp64_value: the FP64 "
+                "contraction on the same quartets",
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -532,7 +677,7 @@ def main():
     ap.add_argument("--pipeline", action="store_true",
                     help="run the next slice's radial derivatives on a second stream while the current "
                          "slice contracts (launch timings then overlap)")
-    ap.add_argument("--workload", choices=("plain", "batched"), default="plain",
+    ap.add_argument("--workload", choices=("plain", "batched", "precision"), default="plain",
                     help="plain: the 20-atom molecule through per-shape launches (default); batched: the "
                          "20-, 10- and 35-atom molecules, each class in one captured graph per step")
     ap.add_argument("--slices", type=int, default=64, help="batched: steps that cover the whole job")
@@ -551,6 +696,9 @@ def main():
         return
     if args.workload == "batched":
         batched_main(args)
+        return
+    if args.workload == "precision":
+        precision_main(args)
         return
 
     import torch

@@ -184,6 +184,25 @@ void f12_quartets_destroy(f12_quartets *q);
 int f12_eval(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
              double *d_out, int64_t out_capacity, void *stream);
 
+/* Arithmetic of the E.R.E contraction (Eq. (ii)). */
+typedef enum {
+  F12_FP64 = 0,       /* every step in binary64                                   */
+  F12_SPLIT_FP32 = 1  /* the ket transform (the one-centre z, y, x passes applied   */
+                      /* to each primitive quartet's Hermite integrals) in split     */
+                      /* FP32: each value a float pair hi + lo (about 48 bits),      */
+                      /* products made exact by fma, sums by two-sum; the integrals  */
+                      /* R_tuv are scaled by an exact power of two per primitive     */
+                      /* quartet to stay in float range.  Radial derivatives, R_tuv, */
+                      /* E coefficients, the bra transform and every sum over        */
+                      /* primitives stay in binary64.                                */
+} f12_precision;
+
+/* f12_eval with the contraction arithmetic chosen by `precision`
+ * (F12_FP64 gives exactly f12_eval's result).  F12_EINVAL for an unknown
+ * precision; otherwise as f12_eval. */
+int f12_eval_precision(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
+                       double *d_out, int64_t out_capacity, int32_t precision, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * evaluation as f12_eval, with the same arguments and output, but the radial-

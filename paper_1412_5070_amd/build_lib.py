@@ -10,7 +10,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libf12int.so")
-SOURCES = ["f12_host.cpp", "f12_batch.cpp", "f12_kernels.hip", "f12_k2.hip"] + ["f12_big_lab%d.hip" % k for k in range(7)]
+SOURCES = ["f12_host.cpp", "f12_batch.cpp", "f12_kernels.hip", "f12_k2.hip"] + ["f12_big_lab%d.hip" % k for k in range(7)] + \
+    ["f12_big_ff%d.hip" % k for k in range(7)]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
 

@@ -27,6 +27,8 @@
 //   comp 0: (a-b)/(2p) E^ab with R_lap = R_{t+2,u,v} + R_{t,u+2,v} + R_{t,u,v+2},
 //   comp d: -F^ab_d with R shifted by one along d.
 #pragma once
+#include <type_traits>
+
 #include "f12_common.h"
 
 namespace f12 {
@@ -119,10 +121,54 @@ struct BigShape {
   static_assert(max_nab(BLAB) * max_nf(LCD) <= DBL - oRp, "(ab|f) staging must fit");
 };
 
-template <int NCOL, int STRIDE>
-__device__ __forceinline__ void load_col(const double *p, int last, double (&c)[NCOL]) {
+template <int NCOL, int STRIDE, typename T>
+__device__ __forceinline__ void load_col(const T *p, int last, T (&c)[NCOL]) {
 #pragma unroll
-  for (int w = 0; w < NCOL; ++w) c[w] = (w <= last) ? p[w * STRIDE] : 0.0;
+  for (int w = 0; w < NCOL; ++w) c[w] = (w <= last) ? p[w * STRIDE] : T{};
+}
+
+// ---------------------------------------------------------------------------
+// Split-FP32 ("float-float") arithmetic for the ket transform of PREC = 1: a
+// value is hi + lo with two floats (about 48 significant bits).  A product is
+// made exact with one fma (Dekker's two-product), sums by Knuth's two-sum,
+// then renormalised.  Contraction of a*b + c into fma is switched off so that
+// the error-free transforms hold.
+// ---------------------------------------------------------------------------
+struct ff {
+  float hi, lo;
+};
+
+__device__ __forceinline__ ff ff_from(double x) {
+  const float h = (float)x;
+  return ff{h, (float)(x - (double)h)};
+}
+
+__device__ __forceinline__ double ff_to(ff a) { return (double)a.hi + (double)a.lo; }
+
+// c + a b
+__device__ __forceinline__ ff ff_fma(ff a, ff b, ff c) {
+#pragma clang fp contract(off)
+  const float p = a.hi * b.hi;
+  float e = __builtin_fmaf(a.hi, b.hi, -p);
+  e = __builtin_fmaf(a.hi, b.lo, e);
+  e = __builtin_fmaf(a.lo, b.hi, e);
+  const float s = c.hi + p;
+  const float bb = s - c.hi;
+  float t = (c.hi - (s - bb)) + (p - bb);
+  t = t + (c.lo + e);
+  const float h = s + t;
+  return ff{h, t - (h - s)};
+}
+
+// 2^-e with e the binary exponent of max_n |A_n|, n = 0..L: the power-of-two
+// scale that brings one primitive quartet's Hermite integrals into float range
+// (exact, so it changes no digit).
+template <int L>
+__device__ __forceinline__ double pq_scale(const double *A) {
+  double m = 0.0;
+#pragma unroll
+  for (int n = 0; n <= L; ++n) m = fmax(m, fabs(A[n]));
+  return m > 0.0 ? ldexp(1.0, -ilogb(m)) : 1.0;
 }
 
 // c(T, i) = T! / (i! (T - 2i)! 2^i): the coefficient of X^(T-2i) D^(T-i) in
@@ -215,9 +261,14 @@ __device__ __forceinline__ void r_line(int T, int U, double Y, double Z, const d
   }
 }
 
-template <int LAB, int LCD, int MODE, int NJ>
+// PREC: 0 = FP64 throughout; 1 = the ket transform (z, y, x passes, one per
+// primitive quartet) in split FP32 on power-of-two-scaled Hermite integrals,
+// with the Hermite integrals themselves, the E coefficients, the bra transform
+// and every accumulation over primitives in FP64.
+template <int LAB, int LCD, int MODE, int NJ, int PREC>
 __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
   using S = BigShape<LAB, LCD, MODE, NJ>;
+  using VT = typename std::conditional<PREC == 1, ff, double>::type;
   constexpr int NT = S::NT, LP = S::LP, L = S::L, NE = S::NE;
   constexpr bool I5 = S::I5;
   constexpr int BLAB = S::BLAB;
@@ -392,6 +443,7 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
           Xj1[jj] = KD[jk * S::KDW + 1] - Pb1;
           Xj2[jj] = KD[jk * S::KDW + 2] - Pb2;
           ckdj[jj] = ok ? KD[jk * S::KDW + 5] : 0.0;
+          if constexpr (PREC == 1) ckdj[jj] /= pq_scale<L>(AS + jk * (L + 1));  // undo the ket scale
           ajj[jj] = jk * (L + 1);
         }
         if (tid < 3 * NJ) {
@@ -412,8 +464,9 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
           const int r = k - jj * ((L + 1) * (L + 1));
           const int T = r / (L + 1), n = r - (r / (L + 1)) * (L + 1);
           const int jk = jk0 + jj;
-          lds[S::oRp + jj * S::PJ + S::jG + T * (L + 1) + n] =
-              g_entry<L>(T, n, KD[jk * S::KDW + 0] - Pb0, AS + jk * (L + 1), hc);
+          double gv = g_entry<L>(T, n, KD[jk * S::KDW + 0] - Pb0, AS + jk * (L + 1), hc);
+          if constexpr (PREC == 1) gv *= pq_scale<L>(AS + jk * (L + 1));
+          lds[S::oRp + jj * S::PJ + S::jG + T * (L + 1) + n] = gv;
         }
         __syncthreads();
         for (int k = tid; k < nvj * S::NLP; k += NT) {
@@ -439,6 +492,25 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
             r_line<L, LP + 1, 0>(T + dt, U + du, Y, Zc, G + (T + dt) * (L + 1), hc, rl);
           }
           const double *ez = base + S::jEk + 2 * NE;
+          if constexpr (PREC == 1) {
+            ff ezr[NE], rlf[LP + 1];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) ezr[e] = ff_from(ez[e]);
+#pragma unroll
+            for (int w = 0; w <= LP; ++w) rlf[w] = ff_from(rl[w]);
+            ff *zo = (ff *)(base + S::jZ + zline * S::ZST);
+#pragma unroll
+            for (int v = 0; v <= LAB; ++v) {
+#pragma unroll
+              for (int fz = 0; fz <= LCD; ++fz) {
+                ff acc{0.f, 0.f};
+#pragma unroll
+                for (int ph = 0; ph <= fz; ++ph)
+                  if (v + ph <= LP) acc = ff_fma(ezr[fz * (fz + 1) / 2 + ph], rlf[v + ph], acc);
+                zo[v * (LCD + 1) + fz] = acc;
+              }
+            }
+          } else {
           double ezr[NE];
 #pragma unroll
           for (int e = 0; e < NE; ++e) ezr[e] = ez[e];
@@ -454,6 +526,7 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
               zo[v * (LCD + 1) + fz] = acc;
             }
           }
+          }
         }
         __syncthreads();
         // y pass
@@ -461,9 +534,15 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
         for (int jj = 0; jj < NJ; ++jj) {
           if (jj >= nvj) break;
           double *base = lds + S::oRp + jj * S::PJ;
-          double ey[NE];
+          VT ey[NE];
 #pragma unroll
-          for (int k = 0; k < NE; ++k) ey[k] = base[S::jEk + NE + k];
+          for (int k = 0; k < NE; ++k) {
+            if constexpr (PREC == 1)
+              ey[k] = ff_from(base[S::jEk + NE + k]);
+            else
+              ey[k] = base[S::jEk + NE + k];
+          }
+          VT *zb = (VT *)(base + S::jZ);
           for (int k = tid; k < S::NYT; k += NT) {
             // T fastest: the lanes of a wave share (v, fz) in runs
             const int T = k % (LP + 1);
@@ -471,9 +550,9 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
             const int v = r1 % (LAB + 1), fz = r1 / (LAB + 1);
             if (T + v + fz > LP) continue;
             const int line0 = T * (LP + 1) - T * (T - 1) / 2;
-            double col[LP + 1];
-            load_col<LP + 1, S::ZST>(base + S::jZ + line0 * S::ZST + v * (LCD + 1) + fz, LP - T, col);
-            double *yo = base + S::jY + T * S::YST + v * NE + fz;
+            VT col[LP + 1];
+            load_col<LP + 1, S::ZST>(zb + line0 * S::ZST + v * (LCD + 1) + fz, LP - T, col);
+            VT *yo = (VT *)(base + S::jY) + T * S::YST + v * NE + fz;
 #pragma unroll
             for (int u = 0; u <= LAB; ++u) {
               if (u + v > LAB) continue;
@@ -481,9 +560,14 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
 #pragma unroll
               for (int fy = 0; fy <= LCD; ++fy) {
                 if (fy + fz > LCD) continue;
-                double acc = 0.0;
+                VT acc{};
 #pragma unroll
-                for (int nu = 0; nu <= fy; ++nu) acc = fma(ey[fy * (fy + 1) / 2 + nu], col[u + nu], acc);
+                for (int nu = 0; nu <= fy; ++nu) {
+                  if constexpr (PREC == 1)
+                    acc = ff_fma(ey[fy * (fy + 1) / 2 + nu], col[u + nu], acc);
+                  else
+                    acc = fma(ey[fy * (fy + 1) / 2 + nu], col[u + nu], acc);
+                }
                 yo[uo + fy * (LCD + 1) - fy * (fy - 1) / 2] = acc;
               }
             }
@@ -495,10 +579,15 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
         for (int jj = 0; jj < NJ; ++jj) {
           if (jj >= nvj) break;
           const double *base = lds + S::oRp + jj * S::PJ;
-          const double *Yb = base + S::jY;
-          double ex[NE];
+          const VT *Yb = (const VT *)(base + S::jY);
+          VT ex[NE];
 #pragma unroll
-          for (int k = 0; k < NE; ++k) ex[k] = base[S::jEk + k];
+          for (int k = 0; k < NE; ++k) {
+            if constexpr (PREC == 1)
+              ex[k] = ff_from(base[S::jEk + k]);
+            else
+              ex[k] = base[S::jEk + k];
+          }
 #pragma unroll
           for (int fx = 0; fx <= LCD; ++fx) {
 #pragma unroll
@@ -506,10 +595,18 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
               const int slot = S::off_fx(fx) + k;
               const int yb = ybase[slot];
               if (yb >= 0) {
-                double acc = 0.0;
+                VT acc{};
 #pragma unroll
-                for (int ta = 0; ta <= fx; ++ta) acc = fma(ex[fx * (fx + 1) / 2 + ta], Yb[yb + ta * S::YST], acc);
-                wacc[slot] = fma(ckdj[jj], acc, wacc[slot]);
+                for (int ta = 0; ta <= fx; ++ta) {
+                  if constexpr (PREC == 1)
+                    acc = ff_fma(ex[fx * (fx + 1) / 2 + ta], Yb[yb + ta * S::YST], acc);
+                  else
+                    acc = fma(ex[fx * (fx + 1) / 2 + ta], Yb[yb + ta * S::YST], acc);
+                }
+                if constexpr (PREC == 1)
+                  wacc[slot] = fma(ckdj[jj], ff_to(acc), wacc[slot]);
+                else
+                  wacc[slot] = fma(ckdj[jj], acc, wacc[slot]);
               }
             }
           }
@@ -624,20 +721,20 @@ constexpr int pick_nj() {
   return 1;
 }
 
-template <int LAB, int LCD, int MODE>
+template <int LAB, int LCD, int MODE, int PREC>
 inline int launch_big_t(const ContractArgs &a, unsigned nblocks, hipStream_t st) {
   constexpr int NJ = pick_nj<LAB, LCD, MODE>();
   using S = BigShape<LAB, LCD, MODE, NJ>;
   static_assert(S::BYTES <= 160 * 1024, "LDS per work-group");
   static bool attr = false;
   if (!attr) {
-    if (hipFuncSetAttribute((const void *)big_kernel<LAB, LCD, MODE, NJ>,
+    if (hipFuncSetAttribute((const void *)big_kernel<LAB, LCD, MODE, NJ, PREC>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::BYTES) != hipSuccess)
       return -1;
     attr = true;
   }
   if (nblocks == 0) return 0;  // set-up only (before a graph capture)
-  hipLaunchKernelGGL((big_kernel<LAB, LCD, MODE, NJ>), dim3(nblocks), dim3(256), S::BYTES, st, a);
+  hipLaunchKernelGGL((big_kernel<LAB, LCD, MODE, NJ, PREC>), dim3(nblocks), dim3(256), S::BYTES, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -648,13 +745,13 @@ constexpr bool lap_fits() {
   return S::BYTES <= 160 * 1024 && S::MAXW <= 40 && S::MAXU <= 32;
 }
 
-template <int LAB>
+template <int LAB, int PREC>
 inline int launch_big_lab(int lcd, int i5, const ContractArgs &a, unsigned nblocks, hipStream_t st) {
-#define F12_BIG_CASE(LCD)                                                                 \
-  case LCD:                                                                               \
-    if (!i5) return launch_big_t<LAB, LCD, 0>(a, nblocks, st);                            \
-    if constexpr (lap_fits<LAB, LCD>()) return launch_big_t<LAB + 2, LCD, 2>(a, nblocks, st); \
-    else return launch_big_t<LAB, LCD, 1>(a, nblocks, st);
+#define F12_BIG_CASE(LCD)                                                                       \
+  case LCD:                                                                                     \
+    if (!i5) return launch_big_t<LAB, LCD, 0, PREC>(a, nblocks, st);                            \
+    if constexpr (lap_fits<LAB, LCD>()) return launch_big_t<LAB + 2, LCD, 2, PREC>(a, nblocks, st); \
+    else return launch_big_t<LAB, LCD, 1, PREC>(a, nblocks, st);
   switch (lcd) {
     F12_BIG_CASE(0)
     F12_BIG_CASE(1)

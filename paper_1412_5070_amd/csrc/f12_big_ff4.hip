@@ -1,0 +1,11 @@
+// Contraction kernels specialised for l_a + l_b = 4 (all l_c + l_d, I1-I6),
+// with the ket transform in split FP32.
+#include "f12_big.h"
+
+namespace f12 {
+
+int launch_big_ff4(int lcd, int i5, const ContractArgs &a, unsigned nblocks, hipStream_t st) {
+  return launch_big_lab<4, 1>(lcd, i5, a, nblocks, st);
+}
+
+}  // namespace f12

@@ -127,6 +127,7 @@ struct ContractArgs {
   int la, lb, lc, ld, i5;
   double *out;
   int64_t out_base;
+  int prec;  // 0: FP64; 1: ket transform in split FP32
 };
 
 // Position of one-centre component (fx, fy, fz) among |f| = l_c .. l_c+l_d.

@@ -729,7 +729,7 @@ int finish_quartets(f12_quartets *Q, std::vector<int64_t> &qb, std::vector<int64
 // Evaluates [q_begin, q_end) with radial-derivative scratch A of cap_prims
 // primitive quartets (times LTOT_MAX + 1 doubles), in chunks that fit it.
 int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_end, double *d_out,
-               double *A, int64_t cap_prims, hipStream_t st);
+               double *A, int64_t cap_prims, hipStream_t st, int prec = 0);
 
 }  // namespace
 
@@ -1068,7 +1068,7 @@ extern "C" void f12_quartets_destroy(f12_quartets *q) { delete q; }
 namespace {
 
 int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_end, double *d_out,
-               double *A, int64_t cap_prims, hipStream_t st) {
+               double *A, int64_t cap_prims, hipStream_t st, int prec) {
   const PairsDev bra = Q->bra->dev(), ket = Q->ket->dev();
   const int i5 = (Q->cls == 5);
   const int64_t out_base = Q->qoff[q_begin];
@@ -1090,7 +1090,7 @@ int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_
         return F12_EDEVICE;
       if (launch_contract(bra, ket, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qoff.ptr, Q->d_qprim.ptr, qa,
                           qe - qa, p0, np, A, b.la, b.lb, b.lc, b.ld, i5, d_out, out_base,
-                          st) != 0)
+                          st, 0, prec) != 0)
         return F12_EDEVICE;
       qa = qe;
     }
@@ -1108,6 +1108,17 @@ extern "C" int f12_eval(f12_quartets *q, const f12_kernel *k, int64_t q_begin, i
   if (q_begin == q_end) return F12_OK;
   q->stage_qa = q->stage_qe = -1;
   return eval_range(q, k, q_begin, q_end, d_out, q->d_A.ptr, q->a_cap_prims, (hipStream_t)stream);
+}
+
+extern "C" int f12_eval_precision(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,
+                                  double *d_out, int64_t out_capacity, int32_t precision, void *stream) {
+  if (precision != F12_FP64 && precision != F12_SPLIT_FP32) return F12_EINVAL;
+  if (!q || !k || !d_out || q_begin < 0 || q_end > q->nq || q_begin > q_end) return F12_EINVAL;
+  if (k->cls != q->cls) return F12_EINVAL;
+  if (q->qoff[q_end] - q->qoff[q_begin] > out_capacity) return F12_EBUFSIZE;
+  if (q_begin == q_end) return F12_OK;
+  q->stage_qa = q->stage_qe = -1;
+  return eval_range(q, k, q_begin, q_end, d_out, q->d_A.ptr, q->a_cap_prims, (hipStream_t)stream, precision);
 }
 
 extern "C" int f12_eval_stage(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,

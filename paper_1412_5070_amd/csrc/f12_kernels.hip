@@ -551,8 +551,27 @@ int launch_big_lab3(int, int, const ContractArgs &, unsigned, hipStream_t);
 int launch_big_lab4(int, int, const ContractArgs &, unsigned, hipStream_t);
 int launch_big_lab5(int, int, const ContractArgs &, unsigned, hipStream_t);
 int launch_big_lab6(int, int, const ContractArgs &, unsigned, hipStream_t);
+int launch_big_ff0(int, int, const ContractArgs &, unsigned, hipStream_t);
+int launch_big_ff1(int, int, const ContractArgs &, unsigned, hipStream_t);
+int launch_big_ff2(int, int, const ContractArgs &, unsigned, hipStream_t);
+int launch_big_ff3(int, int, const ContractArgs &, unsigned, hipStream_t);
+int launch_big_ff4(int, int, const ContractArgs &, unsigned, hipStream_t);
+int launch_big_ff5(int, int, const ContractArgs &, unsigned, hipStream_t);
+int launch_big_ff6(int, int, const ContractArgs &, unsigned, hipStream_t);
 
 static int launch_big(int lab, int lcd, int i5, const ContractArgs &a, unsigned nb, hipStream_t st) {
+  if (a.prec == 1) {
+    switch (lab) {
+      case 0: return launch_big_ff0(lcd, i5, a, nb, st);
+      case 1: return launch_big_ff1(lcd, i5, a, nb, st);
+      case 2: return launch_big_ff2(lcd, i5, a, nb, st);
+      case 3: return launch_big_ff3(lcd, i5, a, nb, st);
+      case 4: return launch_big_ff4(lcd, i5, a, nb, st);
+      case 5: return launch_big_ff5(lcd, i5, a, nb, st);
+      case 6: return launch_big_ff6(lcd, i5, a, nb, st);
+      default: return -1;
+    }
+  }
   switch (lab) {
     case 0: return launch_big_lab0(lcd, i5, a, nb, st);
     case 1: return launch_big_lab1(lcd, i5, a, nb, st);
@@ -568,7 +587,7 @@ static int launch_big(int lab, int lcd, int i5, const ContractArgs &a, unsigned 
 int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb, const int64_t *qk,
                     const int64_t *qoff, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
                     int64_t np, const double *A, int la, int lb, int lc, int ld, int i5,
-                    double *out, int64_t out_base, hipStream_t stream, int64_t grid) {
+                    double *out, int64_t out_base, hipStream_t stream, int64_t grid, int prec) {
   if (nqc <= 0) return 0;
   ContractArgs a;
   a.bra = bra;
@@ -589,6 +608,7 @@ int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
   a.i5 = i5;
   a.out = out;
   a.out_base = out_base;
+  a.prec = prec;
   // grid > 0: persistent work-groups (at most grid of them); grid == 0: one
   // work-group per quartet; grid < 0: set the kernel's attributes only
   const int64_t nb = grid < 0 ? 0 : (grid == 0 ? nqc : (grid < nqc ? grid : nqc));

@@ -19,7 +19,8 @@ int launch_aux(const KernelDev *K, const PairsDev &bra, const PairsDev &ket, con
 int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb, const int64_t *qk,
                     const int64_t *qoff, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
                     int64_t np, const double *A, int la, int lb, int lc, int ld, int i5,
-                    double *out, int64_t out_base, hipStream_t stream, int64_t grid = 0);
+                    double *out, int64_t out_base, hipStream_t stream, int64_t grid = 0,
+                    int prec = 0);
 
 // Radial derivatives A_n (n = 0..L) for explicit (p, q, R) triples (diagnostic path).
 int launch_aux_points(const KernelDev *K, int64_t n, const double *p, const double *q,

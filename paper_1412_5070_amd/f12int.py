@@ -55,6 +55,7 @@ EXPORTS = {
     "f12_quartets_prim_count": (_c_i32, [_vp, _P(_c_i64)]),
     "f12_quartets_destroy": (None, [_vp]),
     "f12_eval": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp]),
+    "f12_eval_precision": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i32, _vp]),
     "f12_eval_noalloc": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp]),
     "f12_eval_stage": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i32, _vp]),
     "f12_quartets_scratch_prims": (_c_i32, [_vp, _P(_c_i64)]),
@@ -280,6 +281,21 @@ def eval_into(quartets, kernel, out, q_begin=0, q_end=None, stream=None):
     assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
     _check(_lib.f12_eval(quartets.handle, kernel.handle, int(q_begin), int(q_end), _vp(out.data_ptr()),
                          out.numel(), _stream_ptr(stream)), "f12_eval")
+    return out
+
+
+FP64, SPLIT_FP32 = 0, 1
+
+
+def eval_precision(quartets, kernel, out, precision, q_begin=0, q_end=None, stream=None):
+    """Enqueue f12_eval_precision: FP64 (0) or the split-FP32 ket transform (1)."""
+    import torch
+    if q_end is None:
+        q_end = quartets.n_quartets
+    assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+    _check(_lib.f12_eval_precision(quartets.handle, kernel.handle, int(q_begin), int(q_end),
+                                   _vp(out.data_ptr()), out.numel(), int(precision), _stream_ptr(stream)),
+           "f12_eval_precision")
     return out
 
 

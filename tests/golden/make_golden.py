@@ -22,6 +22,8 @@ Sets:
   deephl   deep high-l contractions (deephl_shells): (dd|dd), (dd|ff), (fd|ff)
            and (ff|ff) with 36 ket primitive pairs, (ff|ff) and (fd|fd) with 36
            bra primitive pairs, and (sp|dd) with 1e4 exponents; I2-I6, P1.
+  prec35   quartets sampled from the 35-atom molecule (seed 5072) of the
+           precision workload, as plain20 samples the 20-atom one; I2-I6, P1.
   factors  the 3-atom s+p molecule (seed 1412) with the other factor sets:
            P2 (non-integer rho < -1) for I2, I3, I5; P4 (integer rho >= 0)
            for I2-I6; the mixed pair (f, f') = (P1, P4) for I4 and I6; I3
@@ -109,8 +111,9 @@ def tinyall_quads(cls):
 DEEP_QUADS = [(1, 1, 2, 3), (1, 1, 4, 4), (0, 1, 2, 2)]
 
 
-def plain20_quads(n_per_L=2, max_prim=64, seed=99):
-    _, shells = config_plain()
+def plain20_quads(n_per_L=2, max_prim=64, seed=99, shells=None):
+    if shells is None:
+        _, shells = config_plain()
     ls = np.array([s.l for s in shells])
     ks = np.array([len(s.exps) for s in shells])
     rng = np.random.default_rng(seed)
@@ -135,6 +138,13 @@ def plain20_quads(n_per_L=2, max_prim=64, seed=99):
     return [q for L in sorted(by_L) for q in by_L[L]]
 
 
+def prec35_quads():
+    """Two quartets per total angular momentum from the 35-atom molecule, at
+    most 64 primitive quartets each (seed 98)."""
+    from synth import config_precision
+    return plain20_quads(seed=98, shells=config_precision()[1])
+
+
 # the "factors" set: (class, f, f') and the tiny molecule's quartets
 FACTOR_CASES = [(2, "P2", "P2"), (3, "P2", "P2"), (5, "P2", "P2"), (2, "P4", "P4"), (3, "P4", "P4"),
                 (4, "P4", "P4"), (5, "P4", "P4"), (6, "P4", "P4"), (4, "P1", "P4"), (6, "P1", "P4")]
@@ -156,6 +166,9 @@ def _job(args):
     if setname == "tinyall":
         from synth import tiny_config
         shells = tiny_config()[1]
+    elif setname == "prec35":
+        from synth import config_precision
+        shells = config_precision()[1]
     else:
         shells = {"df3": df3_shells, "deep": deep_shells, "deephl": deephl_shells}.get(
             setname, lambda: config_plain()[1])()
@@ -174,6 +187,10 @@ def build(setname):
         jobs = [(setname, c, q) for c in (5, 1, 2, 3, 4, 6) for q in tinyall_quads(c)]
     elif setname == "deephl":
         jobs = [(setname, c, q) for c in (5, 2, 3, 4, 6) for q in DEEPHL_QUADS]
+    elif setname == "prec35":
+        from synth import config_precision
+        quads = prec35_quads()
+        jobs = [(setname, c, q) for c in (5, 2, 3, 4, 6) for q in quads]
     elif setname == "factors":
         cases = list(FACTOR_CASES) + [(3, f, fp) for (c, f, fp) in FACTOR_CASES if c == 5]
         jobs = [(setname, c, q, f, fp) for (c, f, fp) in cases for q in FACTOR_QUADS]
