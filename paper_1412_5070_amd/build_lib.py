@@ -21,8 +21,19 @@ def build(verbose=False, jobs=None):
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
 
+    # with F12_INCREMENTAL=1, an object newer than its source and every header
+    # is kept (a development aid; the default always compiles everything)
+    incremental = os.environ.get("F12_INCREMENTAL") == "1"
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    headers.append(os.path.join(os.path.dirname(HERE), "include", "f12int.h"))
+    newest_h = max(os.path.getmtime(h) for h in headers)
+
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        if incremental and os.path.exists(obj):
+            t = os.path.getmtime(obj)
+            if t > os.path.getmtime(os.path.join(CSRC, src)) and t > newest_h:
+                return src, obj, subprocess.CompletedProcess([], 0, "", "")
         cmd = [hipcc] + FLAGS + ["-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         return src, obj, r

@@ -45,8 +45,12 @@ struct DevBuf {
 
 inline int ncart_host(int l) { return (l + 1) * (l + 2) / 2; }
 
+// One term c r^alpha e^{b r - g r^2}; the coefficient is the double-double
+// c + clo (the expansion keeps it to about 32 digits, so that the
+// singular parts of terms with negative powers cancel to that precision).
 struct HostTerm {
   double c, alpha, b, g;
+  double clo = 0.0;
 };
 
 struct Bin {

@@ -188,11 +188,20 @@ using Expr = std::vector<HostTerm>;  // sum c r^alpha exp(b r - g r^2)
 
 bool same(double x, double y) { return std::fabs(x - y) <= 1e-12 * (1.0 + std::fabs(x) + std::fabs(y)); }
 
+inline dd tc(const HostTerm &t) { return dd{t.c, t.clo}; }
+inline HostTerm term(dd c, double alpha, double b, double g) {
+  HostTerm t{c.hi, alpha, b, g};
+  t.clo = c.lo;
+  return t;
+}
+
 void add_term(Expr &e, HostTerm t) {
-  if (t.c == 0.0) return;
+  if (t.c == 0.0 && t.clo == 0.0) return;
   for (auto &u : e)
     if (same(u.alpha, t.alpha) && same(u.b, t.b) && same(u.g, t.g)) {
-      u.c += t.c;
+      const dd s = dd_add(tc(u), tc(t));
+      u.c = s.hi;
+      u.clo = s.lo;
       return;
     }
   e.push_back(t);
@@ -201,7 +210,7 @@ void add_term(Expr &e, HostTerm t) {
 Expr mul(const Expr &x, const Expr &y) {
   Expr r;
   for (auto &a : x)
-    for (auto &b : y) add_term(r, {a.c * b.c, a.alpha + b.alpha, a.b + b.b, a.g + b.g});
+    for (auto &b : y) add_term(r, term(dd_mul(tc(a), tc(b)), a.alpha + b.alpha, a.b + b.b, a.g + b.g));
   return r;
 }
 
@@ -209,9 +218,9 @@ Expr mul(const Expr &x, const Expr &y) {
 Expr deriv(const Expr &x) {
   Expr r;
   for (auto &t : x) {
-    add_term(r, {t.c * t.alpha, t.alpha - 1.0, t.b, t.g});
-    add_term(r, {t.c * t.b, t.alpha, t.b, t.g});
-    add_term(r, {-2.0 * t.c * t.g, t.alpha + 1.0, t.b, t.g});
+    add_term(r, term(dd_mul(tc(t), t.alpha), t.alpha - 1.0, t.b, t.g));
+    add_term(r, term(dd_mul(tc(t), t.b), t.alpha, t.b, t.g));
+    add_term(r, term(dd_mul(tc(t), -2.0 * t.g), t.alpha + 1.0, t.b, t.g));
   }
   return r;
 }
@@ -229,10 +238,10 @@ Expr factor_expr(const f12_factor &f) {
   add_term(e, {0.5, 1.0, 0.0, f.mu});
   if (f.c0 != 0.0) {
     add_term(e, {f.c0, f.rho, f.B, 0.0});
-    double mk = 1.0;
+    dd mk = dd_make(1.0);  // mu^k / k!
     for (int k = 0; k <= f.n; ++k) {
-      if (k > 0) mk *= f.mu / k;
-      add_term(e, {-f.c0 * mk, f.rho + 2.0 * k, f.B, f.mu});
+      if (k > 0) mk = dd_div(dd_mul(mk, f.mu), (double)k);
+      add_term(e, term(dd_mul(mk, -f.c0), f.rho + 2.0 * k, f.B, f.mu));
     }
   }
   return e;
@@ -370,6 +379,147 @@ double w_phi_series_dd(double a, double x) {
   return dd_to_double(dd_mul(dd_mul(sum, e), 0.5));
 }
 
+// Gauss-Legendre rule of 20 points on [-1, 1] in long double (Newton on P_20).
+struct GL20 {
+  ld x[20], w[20];
+  GL20() {
+    const int n = 20;
+    for (int k = 0; k < n; ++k) {
+      ld z = cosl(3.14159265358979323846264338327950288L * (k + 0.75L) / (n + 0.5L));
+      for (int it = 0; it < 100; ++it) {
+        ld p0 = 1, p1 = z;
+        for (int j = 2; j <= n; ++j) {
+          ld p2 = ((2 * j - 1) * z * p1 - (j - 1) * p0) / j;
+          p0 = p1;
+          p1 = p2;
+        }
+        ld dp = n * (z * p1 - p0) / (z * z - 1);
+        ld dz = p1 / dp;
+        z -= dz;
+        if (fabsl(dz) < 1e-21L) break;
+      }
+      ld p0 = 1, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        ld p2 = ((2 * j - 1) * z * p1 - (j - 1) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      ld dp = n * (z * p1 - p0) / (z * z - 1);
+      x[k] = z;
+      w[k] = 2 / ((1 - z * z) * dp * dp);
+    }
+  }
+};
+
+// Finite parts W_{-n}(x) = FP int_0^inf t^{-n} exp(-(t - x)^2) dt, n = 1..nmax
+// (Eq. (sila) with beta = 2x, gamma = 1, times exp(-x^2); the finite part
+// drops the terms in eps^{j-n+1} and log eps of the integral from eps).  With
+// c = 1/(1 + |x|) and H_j the Taylor coefficients of exp(-(t - x)^2) at t = 0,
+//   W_{-n} = sum_{j != n-1} H_j c^{j-n+1} / (j - n + 1) + H_{n-1} log c
+//            + int_c^inf t^{-n} exp(-(t - x)^2) dt,
+// the first sum over all j >= 0 (the part of [0, c] after subtracting the
+// singular terms, plus the finite parts of the subtracted terms), the last
+// integral by Gauss-Legendre panels: geometric (ratio 1.25) from c to 1, then
+// of width 1/4 to max(x, 0) + 12.  H_j = e^{-x^2} Hphys_j(x) / j!.
+void w_negint(int nmax, ld x, ld *out) {
+  static const GL20 gl;
+  const ld c = 1.0L / (1.0L + fabsl(x));
+  const ld ex = expl(-x * x);
+  // q_j = Hphys_j(x) / j!
+  const int J = nmax + 120;
+  std::vector<ld> q(J + 1);
+  q[0] = 1;
+  q[1] = 2 * x;
+  for (int j = 1; j < J; ++j) q[j + 1] = (2 * x * q[j] - 2 * q[j - 1]) / (j + 1);
+  const ld lc = logl(c);
+  for (int n = 1; n <= nmax; ++n) {
+    ld s = 0, cp = powl(c, (ld)(1 - n));  // c^{j-n+1} at j = 0
+    for (int j = 0; j <= J; ++j) {
+      if (j == n - 1)
+        s += q[j] * lc;
+      else
+        s += q[j] * cp / (ld)(j - n + 1);
+      cp *= c;
+    }
+    out[n] = ex * s;
+  }
+  // tail integrals for every n at once
+  std::vector<ld> tail(nmax + 1, 0.0L);
+  auto panel = [&](ld a, ld b) {
+    const ld h = 0.5L * (b - a), m = 0.5L * (a + b);
+    for (int k = 0; k < 20; ++k) {
+      const ld t = m + h * gl.x[k];
+      const ld g = gl.w[k] * h * expl(-(t - x) * (t - x));
+      ld tp = 1.0L / t;
+      for (int n = 1; n <= nmax; ++n) {
+        tail[n] += g * tp;
+        tp /= t;
+      }
+    }
+  };
+  ld a = c;
+  while (a < 1.0L) {
+    const ld b = std::min(1.0L, a * 1.25L);
+    panel(a, b);
+    a = b;
+  }
+  const ld top = std::max(x, (ld)0) + 12.0L;
+  for (; a < top; a += 0.25L) panel(a, a + 0.25L);
+  for (int n = 1; n <= nmax; ++n) out[n] += tail[n];
+}
+
+// Finite parts W_{-n}(x), n = 1..nmax, from the series in powers of x:
+//   W_a(x) = e^{-x^2} sum_k c_{a+k} (2x)^k / k!,  c_m = FP int_0^inf t^m e^{-t^2} dt,
+// c_m = Gamma((m+1)/2)/2, except at m = -(2p+1), where c_m = (-1)^p psi(p+1)/(2 p!)
+// (the finite part of the log-divergent integrals).  Terms k >= n (m >= 0)
+// by the ratio c_{m+2} = (m+1)/2 c_m; everything in double-double, which
+// absorbs the cancellation of the alternating terms k < n.
+void w_negint_series_dd(int nmax, double x, ld *out) {
+  std::vector<dd> cneg(nmax + 1);  // c_{-n}
+  for (int n = 1; n <= nmax; ++n) {
+    if (n & 1) {
+      const int p = (n - 1) / 2;
+      dd psi = dd{-0.5772156649015329, 4.942915152430645e-18};
+      dd pf = dd_make(1.0);
+      for (int i = 1; i <= p; ++i) {
+        psi = dd_add(psi, dd_div(dd_make(1.0), (double)i));
+        pf = dd_mul(pf, (double)i);
+      }
+      dd v = dd_div(dd_mul(psi, 0.5), pf);
+      cneg[n] = (p & 1) ? dd_neg(v) : v;
+    } else {
+      cneg[n] = dd_mul(dd_gamma_any(0.5 - n / 2), 0.5);
+    }
+  }
+  const dd y = dd_make(2.0 * x);
+  const dd y2 = dd_mul(y, y);
+  const dd ex = dd_exp(dd_neg(dd_mul(dd_make(x), x)));
+  const dd c0 = dd_mul(dd_gamma(0.5), 0.5), c1 = dd_make(0.5);  // c_0 = sqrt(pi)/2, c_1 = 1/2
+  const int kextra = (int)(4.0 * x * x) + 60;
+  for (int n = 1; n <= nmax; ++n) {
+    dd sum = dd_make(0.0);
+    // k < n: finite-part coefficients
+    dd pk = dd_make(1.0);  // (2x)^k / k!
+    for (int k = 0; k < n; ++k) {
+      sum = dd_add(sum, dd_mul(cneg[n - k], pk));
+      pk = dd_div(dd_mul(pk, y), (double)(k + 1));
+    }
+    // k >= n: t_k = c_{k-n} (2x)^k / k!, two interleaved ratio chains
+    dd te = dd_mul(c0, pk);                                        // k = n
+    dd to = dd_div(dd_mul(dd_mul(c1, pk), y), (double)(n + 1));    // k = n + 1
+    sum = dd_add(sum, dd_add(te, to));
+    for (int j = 0; j < kextra; j += 2) {
+      const int k = n + j;  // te at k, to at k + 1
+      te = dd_div(dd_mul(dd_mul(te, 0.5 * (j + 1)), y2), (double)(k + 1) * (k + 2));
+      to = dd_div(dd_mul(dd_mul(to, 0.5 * (j + 2)), y2), (double)(k + 2) * (k + 3));
+      sum = dd_add(sum, dd_add(te, to));
+      if (j > 4.0 * x * x + 20 && std::fabs(te.hi) + std::fabs(to.hi) < 1e-34 * std::fabs(sum.hi)) break;
+    }
+    const dd w = dd_mul(sum, ex);
+    out[n] = (ld)w.hi + (ld)w.lo;
+  }
+}
+
 void w_column(double a0, bool is_int, int m_lo, int m_hi, double xd, double *out) {
   const ld x = xd;
   const int n = m_hi - m_lo + 1;
@@ -412,6 +562,53 @@ void w_column(double a0, bool is_int, int m_lo, int m_hi, double xd, double *out
     }
     ld scale = w0 / tr[0];
     for (int m = std::max(0, m_lo); m <= m_hi; ++m) at(m) = tr[m] * scale;
+  }
+  // ---- negative integer orders (finite parts)
+  if (m_lo < 0 && is_int) {
+    const int nmax = -m_lo;
+    std::vector<ld> wn(nmax + 1);
+    if (x > 16.0L) {
+      // the integral is dominated by the peak at t = x: direct formula
+      w_negint(nmax, x, wn.data());
+    } else if (x > 0.5L) {
+      w_negint_series_dd(nmax, (double)x, wn.data());
+    } else {
+      // W_{-1} = e^{-x^2} [int_0^{1/2} expm1(2xt - t^2)/t dt - log 2]
+      //          + int_{1/2}^inf e^{-(t-x)^2}/t dt   (no cancellation for x <= 1/2),
+      // then downward: W_{-n-1} = (2x W_{-n} - 2 W_{-n+1} + H_n) / n, the
+      // integration-by-parts relation with its boundary term H_n (stable here)
+      static const GL20 gl;
+      const ld ex = expl(-x * x);
+      ld near = 0, far = 0;
+      for (int pnl = 0; pnl < 8; ++pnl) {
+        const ld a = pnl / 16.0L, h = 1.0L / 32;
+        for (int k = 0; k < 20; ++k) {
+          const ld t = a + h + h * gl.x[k];
+          near += gl.w[k] * h * expm1l(2 * x * t - t * t) / t;
+        }
+      }
+      for (ld a = 0.5L; a < 12.0L; a += 0.25L) {
+        const ld h = 0.125L;
+        for (int k = 0; k < 20; ++k) {
+          const ld t = a + h + h * gl.x[k];
+          far += gl.w[k] * h * expl(-(t - x) * (t - x)) / t;
+        }
+      }
+      const ld wm1 = ex * (near - logl(2.0L)) + far;
+      ld qm1 = 1, q = 2 * x;  // Hphys_n(x)/n! at n = 0, 1
+      ld wprev = w0, wcur = wm1;
+      wn[1] = wcur;
+      for (int n = 1; n < nmax; ++n) {
+        const ld wnext = (2 * x * wcur - 2 * wprev + ex * q) / n;
+        wn[n + 1] = wnext;
+        wprev = wcur;
+        wcur = wnext;
+        const ld qn = (2 * x * q - 2 * qm1) / (n + 1);
+        qm1 = q;
+        q = qn;
+      }
+    }
+    for (int m = m_lo; m < 0; ++m) at(m) = wn[-m];
   }
   // ---- downward (m < 0), non-integer families only
   if (m_lo < 0 && !is_int) {
@@ -456,7 +653,7 @@ void w_column(double a0, bool is_int, int m_lo, int m_hi, double xd, double *out
 extern "C" int f12_aux_w_column(double alpha0, int32_t is_int, int32_t m_lo, int32_t m_hi,
                                 double x, double *out) {
   if (!out || m_hi < m_lo || m_hi < 1 || alpha0 < 0 || alpha0 >= 1) return F12_EINVAL;
-  if (is_int && m_lo < 0) return F12_EINVAL;
+  if (is_int && m_lo < -64) return F12_EINVAL;
   w_column(alpha0, is_int != 0, m_lo, m_hi, x, out);
   return F12_OK;
 }
@@ -490,7 +687,7 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
   // drop exact cancellations
   Expr e2;
   for (auto &t : e)
-    if (std::fabs(t.c) > 1e-300) e2.push_back(t);
+    if (std::fabs(t.c) > 1e-300) e2.push_back(t);  // exact cancellations
   e = e2;
   K->terms = e;
   // ---- families and chains
@@ -503,7 +700,7 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
   struct Ch {
     double b, g;
     int fam;
-    std::vector<std::pair<int, double>> tm;
+    std::vector<std::pair<int, dd>> tm;
   };
   std::vector<Ch> chains;
   for (auto &t : e) {
@@ -518,8 +715,7 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
       fams.push_back({a0, a0 == 0.0, 1 << 30, -(1 << 30)});
       fi = (int)fams.size() - 1;
     }
-    if (fams[fi].is_int && m < 0) return F12_EPARAM;  // negative integer powers not supported
-    if (t.alpha <= -2.0 + 1e-9) return F12_EPARAM;    // small-T series needs alpha > -2
+    if (m < -NEG_POW_MAX) return F12_EPARAM;  // beyond the tabulated negative orders
     int ci = -1;
     for (size_t i = 0; i < chains.size(); ++i)
       if (chains[i].fam == fi && same(chains[i].b, t.b) && same(chains[i].g, t.g)) ci = (int)i;
@@ -528,7 +724,7 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
       ci = (int)chains.size() - 1;
     }
     if (t.b < 0.0) return F12_EPARAM;  // the ladders assume b >= 0
-    chains[ci].tm.push_back({m, t.c});
+    chains[ci].tm.push_back({m, dd{t.c, t.clo}});
   }
   if ((int)chains.size() > MAX_CHAINS || (int)e.size() > MAX_TERMS ||
       (int)fams.size() > MAX_FAMILIES)
@@ -548,7 +744,8 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
     cd.m_min = 1 << 30;
     cd.m_max = -(1 << 30);
     for (auto &pr : chains[c].tm) {
-      D.terms[nt].c = pr.second;
+      D.terms[nt].c = pr.second.hi;
+      D.terms[nt].clo = pr.second.lo;
       D.terms[nt].m = pr.first;
       D.terms[nt].chain = (int)c;
       ++nt;
@@ -560,11 +757,14 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
     if (cd.m_max - cd.m_min + LTOT_MAX + 1 > NW_MAX) return F12_EPARAM;
     cd.phi_off = (int)c * 2 * (KPHI + 1);
     Fam &F = fams[cd.family];
-    int lo = F.is_int ? 0 : cd.m_min - LTOT_MAX;
+    int lo = (F.is_int && cd.m_min >= 0) ? 0 : cd.m_min - LTOT_MAX;
     F.m_lo = std::min(F.m_lo, lo);
     F.m_hi = std::max(F.m_hi, cd.m_max + KT + 1);
   }
   D.nterms = nt;
+  D.negint = 0;
+  for (int c = 0; c < D.nchains; ++c)
+    if (fams[D.chains[c].family].is_int && D.chains[c].m_min < 0) D.negint = 1;
   // ---- W tables
   const int nx = (int)std::lround((WX_HI - WX_LO) * WX_INVH) + 1;
   for (size_t fi = 0; fi < fams.size(); ++fi) {
@@ -600,7 +800,23 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
       for (int k = 0; k <= KPHI; ++k) {
         if (k > 0) kf = dd_mul(kf, (double)k);
         double arg = 0.5 * (a + 1.0 + k);
-        dd gval = dd_gamma_any(arg);
+        dd gval;
+        const double pr = -arg;  // a pole of Gamma when a non-negative integer
+        if (fams[cd.family].is_int && pr >= 0.0 && pr == std::floor(pr)) {
+          // finite part of int_0^inf t^(-2p-1) e^{-t^2} dt = (-1)^p psi(p+1) / (2 p!):
+          // the Phi-series coefficient takes (-1)^p psi(p+1) / p! for Gamma(-p)
+          const int pp = (int)pr;
+          dd psi = dd{-0.5772156649015329, 4.942915152430645e-18};  // -Euler's gamma
+          dd pf = dd_make(1.0);
+          for (int i = 1; i <= pp; ++i) {
+            psi = dd_add(psi, dd_div(dd_make(1.0), (double)i));
+            pf = dd_mul(pf, (double)i);
+          }
+          gval = dd_div(psi, pf);
+          if (pp & 1) gval = dd_neg(gval);
+        } else {
+          gval = dd_gamma_any(arg);
+        }
         dd v = dd_div(dd_mul(gval, 0.5), kf);
         size_t o = ((size_t)(c * 2 + s) * (KPHI + 1) + k) * 2;
         phi[o] = v.hi;

@@ -10,6 +10,7 @@ constexpr int LTOT_MAX = 4 * LMAX + 2;  // I5 (ff|ff): 14
 constexpr int MAX_CHAINS = 16;
 constexpr int MAX_TERMS = 96;
 constexpr int MAX_FAMILIES = 4;
+constexpr int NEG_POW_MAX = 12;        // most negative integer power of a kernel term
 constexpr int KT = 16;                  // Taylor terms of the W-table interpolation
 constexpr int KPHI = 96;                // terms of the DD Phi-series (small-T route)
 constexpr int NW_MAX = 64;              // orders of W per chain in the large-T route:
@@ -20,7 +21,7 @@ constexpr double WX_INVH = 64.0;        // grid step 1/64
 
 // One term c * r^alpha * exp(b r - g r^2) of K_i(r) = r k_i(r); alpha = alpha0(chain) + m.
 struct TermDesc {
-  double c;
+  double c, clo;  // coefficient as a double-double c + clo
   int32_t m;
   int32_t chain;
 };
@@ -46,12 +47,15 @@ struct FamilyDesc {
 struct KernelDev {
   int32_t cls;
   int32_t nchains, nterms, nfam;
+  int32_t negint;  // 1 if an integer family has negative powers (finite parts with log terms)
   ChainDesc chains[MAX_CHAINS];
   TermDesc terms[MAX_TERMS];
   FamilyDesc fam[MAX_FAMILIES];
   // Phi-series coefficients for the small-T route, DD pairs (hi, lo):
-  // for chain c, start index s in {0,1}: Gamma((a_s + 1 + k)/2) / (2 k!),
-  // a_s = alpha0 + m_min + 1 + s, k = 0..KPHI.
+  // for chain c, start index s in {0,1}: F((a_s + 1 + k)/2) / (2 k!),
+  // a_s = alpha0 + m_min + 1 + s, k = 0..KPHI, with F = Gamma, except at its
+  // poles -p (p = 0, 1, ...), where the finite part of int t^(-2p-1) e^{-t^2}
+  // takes its place: F = (-1)^p psi(p + 1) / p!.
   const double *phi;
 };
 

@@ -104,8 +104,13 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
     const double isq = 1.0 / sqg;
     const double g0 = pow(gam, -0.5 * (F.alpha0 + 1.0));
     int mlo = ch.m_min - L;
-    if (F.is_int && mlo < 0) mlo = 0;
+    if (F.is_int && ch.m_min >= 0 && mlo < 0) mlo = 0;
     const int mhi = ch.m_max;
+    // negative integer powers: finite parts in r, Omega_{-n}(y) =
+    // gam^{(n-1)/2} W_{-n}(sqrt(gam) y) - (1/2) log(gam) h_{n-1}(y), with
+    // h_m(y) = [r^m] e^{-gam (r - y)^2} = gam^{m/2} e^{-X^2} Hphys_m(X) / m!
+    const bool negint = F.is_int && ch.m_min < 0;
+    const double hlg = negint ? 0.5 * log(gam) : 0.0;
     for (int sgn = 1; sgn >= -1; sgn -= 2) {
       if (sgn < 0 && !do_minus) break;
       const double x = sgn * R;
@@ -146,12 +151,43 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
           }
         }
       }
+      // h_m(y), m = 0..-mlo (negative integer powers only)
+      double hh[NW_MAX + 1];
+      if (negint) {
+        const double eX = exp(-X * X);
+        double q0 = 1.0, q1 = 2.0 * X, gpw = 1.0;
+        const double sg = sqrt(gam);
+        for (int m = 0; m <= -mlo; ++m) {
+          const double qm = m == 0 ? q0 : q1;
+          hh[m] = gpw * eX * qm;
+          if (m >= 1) {
+            const double q2 = (2.0 * X * q1 - 2.0 * q0) / (m + 1);
+            q0 = q1;
+            q1 = q2;
+          }
+          gpw *= sg;
+        }
+        for (int m = mlo; m < 0 && m <= mhi; ++m) Om[m - mlo] -= hlg * hh[-m - 1];
+      }
       double Z[LTOT_MAX + 1];
       for (int k = 0; k <= L; ++k) Z[k] = 0.0;
       for (int t = ch.t_begin; t < ch.t_end; ++t) {
         const double ct = K->terms[t].c;
         const int mt = K->terms[t].m;
         const double al = F.alpha0 + mt;
+        if (F.is_int && mt < 0) {
+          // d^k/dy^k Omega_{-n} = (-1)^k (n+k-1)!/(n-1)! [Omega_{-n-k}
+          //   - (sum_{j<k} 1/(n+j)) h_{n+k-1}]  (Omega'_{-n} = -n Omega_{-n-1} + h_n,
+          // h_m' = -(m+1) h_{m+1})
+          const int n = -mt;
+          double pf = 1.0, hs = 0.0;
+          for (int k = 0; k <= L; ++k) {
+            Z[k] += ct * pf * (Om[mt - k - mlo] - hs * hh[n + k - 1]);
+            pf *= -(double)(n + k);
+            hs += 1.0 / (n + k);
+          }
+          continue;
+        }
         double ff = 1.0;
         int klow = L;
         if (F.is_int && mt < L) klow = mt;
@@ -279,6 +315,24 @@ __device__ void aux_small(const KernelDev *__restrict__ K, double xi, double u, 
     }
     dd Sm1 = dd_mul(p0, f0);  // S(a_s)
     dd S0 = dd_mul(p1, f1);   // S(a_s + 1)
+    // integer a_s <= -1 (negative powers): finite parts in r, with the
+    // Taylor coefficients f_m = [r^m] e^{b r - gam r^2},
+    // (m+1) f_{m+1} = b f_m - 2 gam f_{m-1}:
+    //   S(-n) = gam^{(n-1)/2} Phi_{-n}(b / sqrt(gam)) - (1/2) log(gam) f_{n-1},
+    // and the ladder gains + f_{-a} at every integer a <= 0 (the boundary term
+    // of the integration by parts)
+    const bool negint = F.is_int && ch.m_min < 0;
+    const int nneg = negint ? -(ch.m_min + 1) : -1;  // -a_s
+    dd fm[NEG_POW_MAX + 2];
+    if (negint) {
+      fm[0] = dd_make(1.0);
+      if (nneg + 1 >= 1) fm[1] = dd_make(b);
+      for (int m = 1; m < nneg + 1; ++m)
+        fm[m + 1] = dd_div(dd_sub(dd_mul(fm[m], b), dd_mul(dd_mul(fm[m - 1], gam), 2.0)), (double)(m + 1));
+      const dd hl = dd_mul(lg, 0.5);
+      if (nneg >= 1) Sm1 = dd_sub(Sm1, dd_mul(hl, fm[nneg - 1]));
+      if (nneg >= 2) S0 = dd_sub(S0, dd_mul(hl, fm[nneg - 2]));
+    }
     const dd inv2g = dd_div(dd_make(0.5), gam);
     const int span = ch.m_max - ch.m_min;
     const int kmax = span + 2 * J;
@@ -290,11 +344,13 @@ __device__ void aux_small(const KernelDev *__restrict__ K, double xi, double u, 
         const int dk = k - off;
         if (dk >= 0 && !(dk & 1)) {
           const int j = dk >> 1;
-          if (j <= J) M[j] = dd_add(M[j], dd_mul(Sk, K->terms[t].c));
+          if (j <= J) M[j] = dd_add(M[j], dd_mul(Sk, dd{K->terms[t].c, K->terms[t].clo}));
         }
       }
       // advance: S(a_s + k + 2) = ((a_s + k + 1) S(a_s + k) + b S(a_s + k + 1)) / (2 gam)
-      dd Snn = dd_mul(dd_add(dd_mul(Sk, as + k + 1), dd_mul(Snext, b)), inv2g);
+      dd num = dd_add(dd_mul(Sk, as + k + 1), dd_mul(Snext, b));
+      if (negint && nneg - k - 1 >= 0) num = dd_add(num, fm[nneg - k - 1]);
+      dd Snn = dd_mul(num, inv2g);
       Sk = Snext;
       Snext = Snn;
     }
@@ -360,6 +416,18 @@ __device__ void aux_small_f64(const KernelDev *__restrict__ K, double xi, double
       f1 = ph[2 * (KPHI + 1)];
     }
     double Sk = p0 * f0, Snext = p1 * f1;
+    // negative integer powers: finite parts as in aux_small
+    const bool negint = F.is_int && ch.m_min < 0;
+    const int nneg = negint ? -(ch.m_min + 1) : -1;
+    double fm[NEG_POW_MAX + 2];
+    if (negint) {
+      fm[0] = 1.0;
+      if (nneg + 1 >= 1) fm[1] = b;
+      for (int m = 1; m < nneg + 1; ++m) fm[m + 1] = (b * fm[m] - 2.0 * gam * fm[m - 1]) / (m + 1);
+      const double hl = 0.5 * log(gam);
+      if (nneg >= 1) Sk -= hl * fm[nneg - 1];
+      if (nneg >= 2) Snext -= hl * fm[nneg - 2];
+    }
     const double inv2g = 0.5 / gam;
     const int kmax = ch.m_max - ch.m_min + 2 * J;
     for (int k = 0; k <= kmax; ++k) {
@@ -367,7 +435,9 @@ __device__ void aux_small_f64(const KernelDev *__restrict__ K, double xi, double
         const int dk = k - (K->terms[t].m - ch.m_min);
         if (dk >= 0 && !(dk & 1) && (dk >> 1) <= J) M[dk >> 1] = fma(Sk, K->terms[t].c, M[dk >> 1]);
       }
-      const double Snn = ((as + k + 1) * Sk + b * Snext) * inv2g;
+      double num = (as + k + 1) * Sk + b * Snext;
+      if (negint && nneg - k - 1 >= 0) num += fm[nneg - k - 1];
+      const double Snn = num * inv2g;
       Sk = Snext;
       Snext = Snn;
     }
@@ -408,6 +478,17 @@ __device__ __forceinline__ double t_switch(int L) {
                                        3.0, 3.5, 4.0, 4.5, 5.0, 6.0, 6.0};
   return sw[L < 0 ? 0 : (L > LTOT_MAX ? LTOT_MAX : L)];
 }
+// Kernels with negative integer powers: the finite parts of single terms
+// cancel between chains, and the pieces grow like gam^{(n-1)/2} for a power
+// r^{-n}; in the lowering route (binary64) that cancellation is damped by
+// e^{-T} only, so the double-double series (exact to T = 14, with the
+// double-double term coefficients) runs up to T = 14.
+constexpr double TSW_NEGINT = 14.0;
+__device__ __forceinline__ double t_switch_k(const KernelDev *K, int L) {
+  const double sw = t_switch(L);
+  return (K->negint && sw < TSW_NEGINT) ? TSW_NEGINT : sw;
+}
+
 __device__ __forceinline__ bool minus_side_needed(double T, int L) {
   // keep the F(-R) branch while exp(-T) (2T)^L / (2L-1)!! > 1e-19
   double lg = -T;
@@ -450,7 +531,7 @@ __global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__rest
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * F12_NT_AUX;
   const int64_t t = base + tid;
-  const double sw = t_switch(L);
+  const double sw = t_switch_k(K, L);
   if (tid < AUX_BINS) s_cnt[tid] = 0;
   __syncthreads();
   int bin = AUX_BINS - 1;
@@ -501,7 +582,7 @@ __global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__rest
   const double T = xi * u;
   double a[LTOT_MAX + 1];
   if (T < sw) {
-    if (L <= 5 && T < 2.0)
+    if (L <= 5 && T < 2.0 && !K->negint)
       aux_small_f64(K, xi, u, L, T, a);
     else
       aux_small(K, xi, u, L, T, a);
@@ -633,8 +714,8 @@ __global__ void aux_points_kernel(const KernelDev *__restrict__ K, int64_t n,
     for (int k = 0; k <= L; ++k) A[k * n + t] = a[k] * Np;
     return;
   }
-  const bool small = (route == 1) || (route == 0 && T < t_switch(L));
-  if (small && route == 0 && L <= 5 && T < 2.0)
+  const bool small = (route == 1) || (route == 0 && T < t_switch_k(K, L));
+  if (small && route == 0 && L <= 5 && T < 2.0 && !K->negint)
     aux_small_f64(K, xi, u, L, T, a);
   else if (small)
     aux_small(K, xi, u, L, T, a);

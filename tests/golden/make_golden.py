@@ -23,7 +23,11 @@ Sets:
            and (ff|ff) with 36 ket primitive pairs, (ff|ff) and (fd|fd) with 36
            bra primitive pairs, and (sp|dd) with 1e4 exponents; I2-I6, P1.
   prec35   quartets sampled from the 35-atom molecule (seed 5072) of the
-           precision workload, as plain20 samples the 20-atom one; I2-I6, P1.
+           precision workload, two per total angular momentum with at most 8
+           primitive quartets each; I2-I6, P1.
+  negpow   the 3-atom s+p molecule with kernels that have negative integer
+           powers: P3 (rho = -3, n = 2) in I2-I6, P2 in I4/I6 (rho + rho' = -3),
+           and the mixed pairs (P1, P3), (P3, P1); I3 beside the I5 entries.
   factors  the 3-atom s+p molecule (seed 1412) with the other factor sets:
            P2 (non-integer rho < -1) for I2, I3, I5; P4 (integer rho >= 0)
            for I2-I6; the mixed pair (f, f') = (P1, P4) for I4 and I6; I3
@@ -140,9 +144,9 @@ def plain20_quads(n_per_L=2, max_prim=64, seed=99, shells=None):
 
 def prec35_quads():
     """Two quartets per total angular momentum from the 35-atom molecule, at
-    most 64 primitive quartets each (seed 98)."""
+    most 8 primitive quartets each (seed 98)."""
     from synth import config_precision
-    return plain20_quads(seed=98, shells=config_precision()[1])
+    return plain20_quads(seed=98, max_prim=8, shells=config_precision()[1])
 
 
 # the "factors" set: (class, f, f') and the tiny molecule's quartets
@@ -151,13 +155,19 @@ FACTOR_CASES = [(2, "P2", "P2"), (3, "P2", "P2"), (5, "P2", "P2"), (2, "P4", "P4
 FACTOR_QUADS = [(0, 0, 0, 0), (1, 0, 2, 3), (3, 1, 4, 2), (3, 3, 5, 1)]
 
 
+# negative powers in the kernel terms: P3 (rho = -3, n = 2) in every class,
+# P2 (rho = -3/2) in I4 and I6 (rho + rho' = -3)
+NEGPOW_CASES = [(2, "P3", "P3"), (3, "P3", "P3"), (4, "P3", "P3"), (5, "P3", "P3"), (6, "P3", "P3"),
+                (4, "P2", "P2"), (6, "P2", "P2"), (4, "P1", "P3"), (6, "P3", "P1")]
+
+
 def factor_key(cls, f, fp, quad):
     return "c%d_%s_%s_%d_%d_%d_%d" % ((cls, f, fp) + tuple(quad))
 
 
 def _job(args):
     setname, cls, quad = args[:3]
-    if setname == "factors":
+    if setname in ("factors", "negpow"):
         from synth import tiny_config
         f, fp = args[3], args[4]
         sh = [tiny_config()[1][i].as_dict() for i in quad]
@@ -191,8 +201,9 @@ def build(setname):
         from synth import config_precision
         quads = prec35_quads()
         jobs = [(setname, c, q) for c in (5, 2, 3, 4, 6) for q in quads]
-    elif setname == "factors":
-        cases = list(FACTOR_CASES) + [(3, f, fp) for (c, f, fp) in FACTOR_CASES if c == 5]
+    elif setname in ("factors", "negpow"):
+        base = FACTOR_CASES if setname == "factors" else NEGPOW_CASES
+        cases = list(base) + [(3, f, fp) for (c, f, fp) in base if c == 5 and (3, f, fp) not in base]
         jobs = [(setname, c, q, f, fp) for (c, f, fp) in cases for q in FACTOR_QUADS]
     else:
         quads = plain20_quads()
@@ -201,7 +212,7 @@ def build(setname):
     with Pool(int(os.environ.get("GOLDEN_PROCS", "6"))) as pool:
         for args, val in pool.imap_unordered(_job, jobs):
             sname, cls, quad = args[:3]
-            if sname == "factors":
+            if sname in ("factors", "negpow"):
                 out[factor_key(cls, args[3], args[4], quad)] = val
             else:
                 out["c%d_%d_%d_%d_%d" % ((cls,) + tuple(quad))] = val

@@ -89,13 +89,65 @@ def test_aux_table_builder_vs_parabolic_cylinder(alpha0, is_int, m_lo, m_hi, x):
             assert abs(col[i] - ref) <= 3e-16 * abs(ref), (m, col[i], ref)
 
 
+def _w_negint_ref(n, x):
+    """Finite part of int_0^inf t^(-n) e^{-(t-x)^2} dt written out in mpmath:
+    on [0, 1] the Taylor series of the Gaussian integrated term by term (the
+    finite part of int_eps^1 t^(j-n) is 1/(j-n+1), and 0 for j = n-1), plus
+    the regular integral over [1, inf)."""
+    x = mp.mpf(x)
+    s, j = mp.mpf(0), 0
+    # H_j = e^{-x^2} Hphys_j(x) / j!
+    h0, h1 = mp.mpf(1), 2 * x
+    hs = [h0, h1]
+    for j in range(1, 400):
+        hs.append((2 * x * hs[j] - 2 * hs[j - 1]) / (j + 1))
+    for j, hj in enumerate(hs):
+        if j != n - 1:
+            s += hj / (j - n + 1)
+    s *= mp.exp(-x * x)
+    s += mp.quad(lambda t: t ** (-n) * mp.exp(-(t - x) ** 2), [1, max(1, x - 8), max(1, x), max(1, x) + 8, mp.inf])
+    return s
+
+
+@pytest.mark.parametrize("x", [-10.5, -6.2, -2.0, -0.6, 0.0, 0.7, 1.5, 4.0, 9.0, 20.0, 35.9])
+def test_aux_table_negative_integer_orders(x):
+    """The host builder's finite parts W_{-n}(x) (negative integer orders,
+    used by kernels with negative powers of r) against the finite part
+    written out in mpmath at 120 digits, n = 1..26."""
+    from paper_1412_5070_amd import f12int
+    col = f12int.aux_w_column(0.0, 1, -26, 2, x)
+    # the Taylor series at t = 0 alternates with terms up to ~e^{x^2/2}: 120
+    # digits keep the reference exact to double precision over the whole range
+    with mp.workdps(120):
+        for n in range(1, 27):
+            ref = _w_negint_ref(n, x)
+            assert abs(col[26 - n] - ref) <= 2e-15 * abs(ref) + 1e-300, (n, col[26 - n], ref)
+
+
+def test_aux_table_negative_integer_orders_at_zero():
+    """At x = 0 the finite parts are closed forms (Eq. (sila) at beta = 0):
+    FP int t^(-2p-1) e^{-t^2} = (-1)^p psi(p+1) / (2 p!), and
+    int t^(-2p) e^{-t^2} = Gamma(1/2 - p) / 2."""
+    from paper_1412_5070_amd import f12int
+    col = f12int.aux_w_column(0.0, 1, -26, 2, 0.0)
+    with mp.workdps(30):
+        for n in range(1, 27):
+            if n % 2:
+                p = (n - 1) // 2
+                ref = (-1) ** p * mp.digamma(p + 1) / (2 * mp.factorial(p))
+            else:
+                ref = mp.gamma(mp.mpf(1) / 2 - n // 2) / 2
+            assert abs(col[26 - n] - ref) <= 1e-15 * abs(ref), (n, col[26 - n], ref)
+
+
 def test_unsupported_kernel_terms_rejected_before_device():
     """Kernel terms the library does not evaluate return F12_EPARAM during
-    term analysis, before any device work: negative integer powers (factor
-    set P3 with rho = -3) and growing chains with b < 0 (B < 0)."""
+    term analysis, before any device work: a negative integer power below
+    -12 (rho = -13 with n = 6, a valid factor) and growing chains with b < 0
+    (B < 0)."""
     from paper_1412_5070_amd import f12int
-    from synth import FACTOR_SETS, Factor
-    for cls, f in ((3, FACTOR_SETS["P3"]), (2, FACTOR_SETS["P3"]), (3, Factor(0.2, 0.5, -0.3, 0.8, 0))):
+    from synth import Factor
+    for cls, f in ((2, Factor(0.05, -13.0, 0.25, 1.0, 6)), (3, Factor(0.2, 0.5, -0.3, 0.8, 0))):
         with pytest.raises(f12int.F12Error) as e:
             f12int.Kernel(cls, f, f)
         assert e.value.status == -2
