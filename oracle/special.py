@@ -30,21 +30,39 @@ def taylor_g(beta, gamma, K):
 
 
 def S_finite_part(alpha, beta, gamma, dps=40):
+    """S(alpha, beta, gamma) of Eq. (sila), with the finite part for alpha <= -1.
+
+    On [0, 1] the integrand is expanded in the Taylor series of
+    exp(beta x - gamma x^2) and integrated term by term: every term
+    g_k x^(alpha+k) contributes g_k / (alpha + k + 1), its finite part (for
+    alpha + k + 1 = 0 the finite part of int_eps^1 dx/x is 0).  The series
+    converges like g_k (factorially); its terms alternate and grow up to about
+    e^{beta^2/(4 gamma)} or e^{|beta|}, so it is summed with 60 extra digits.
+    The rest, int_1^inf, is a regular integral.  (Subtracting the Taylor
+    polynomial inside a quadrature instead loses all digits when -alpha is
+    more than about 2.)"""
     with mp.workdps(dps):
         a = mp.mpf(alpha)
         beta, gamma = mp.mpf(beta), mp.mpf(gamma)
-        g = lambda x: mp.exp(beta * x - gamma * x * x)
         if a > -1:
-            return mp.quad(lambda x: x ** a * g(x), [0, 1, mp.inf])
-        K = int(mp.ceil(-a)) - 1
-        gk = taylor_g(beta, gamma, K)
-
-        def sub(x):
-            return x ** a * (g(x) - sum(gk[k] * x ** k for k in range(K + 1)))
-
-        val = mp.quad(sub, [0, 1])
-        for k in range(K + 1):
+            return mp.quad(lambda x: x ** a * mp.exp(beta * x - gamma * x * x), [0, 1, mp.inf])
+    with mp.workdps(dps + 60):
+        a = mp.mpf(alpha)
+        b, c = mp.mpf(beta), mp.mpf(gamma)
+        # g_k by (k+1) g_{k+1} = b g_k - 2 c g_{k-1}
+        g0, g1 = mp.mpf(1), b
+        val = mp.mpf(0)
+        k, small = 0, 0
+        while True:
+            gk = g0 if k == 0 else g1
             if a + k + 1 != 0:
-                val += gk[k] / (a + k + 1)
-        val += mp.quad(lambda x: x ** a * g(x), [1, mp.inf])
-        return val
+                val += gk / (a + k + 1)
+            if k >= 1:
+                g0, g1 = g1, (b * g1 - 2 * c * g0) / (k + 1)
+            small = small + 1 if (k > 10 and abs(gk) < mp.mpf(10) ** (-(dps + 30)) * (1 + abs(val))) else 0
+            if small > 4 or k > 20000:
+                break
+            k += 1
+        val += mp.quad(lambda x: x ** a * mp.exp(b * x - c * x * x), [1, 2, 4, mp.inf])
+    with mp.workdps(dps):
+        return +val
