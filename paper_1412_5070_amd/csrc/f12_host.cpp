@@ -763,8 +763,12 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
   }
   D.nterms = nt;
   D.negint = 0;
-  for (int c = 0; c < D.nchains; ++c)
+  D.heavy = 0;
+  for (int c = 0; c < D.nchains; ++c) {
     if (fams[D.chains[c].family].is_int && D.chains[c].m_min < 0) D.negint = 1;
+    if (D.chains[c].m_max - D.chains[c].m_min + LTOT_MAX + 1 > NW_LIGHT) D.heavy = 1;
+  }
+  if (D.negint) D.heavy = 1;
   // ---- W tables
   const int nx = (int)std::lround((WX_HI - WX_LO) * WX_INVH) + 1;
   for (size_t fi = 0; fi < fams.size(); ++fi) {
@@ -1302,7 +1306,7 @@ int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_
       const int64_t p0 = Q->qprim[qa];
       const int64_t np = Q->qprim[qe] - p0;
       if (launch_aux(k->d_desc.ptr, bra, ket, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qprim.ptr, qa,
-                     qe - qa, p0, np, L, A, st) != 0)
+                     qe - qa, p0, np, L, A, st, k->host_desc.heavy) != 0)
         return F12_EDEVICE;
       if (launch_contract(bra, ket, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qoff.ptr, Q->d_qprim.ptr, qa,
                           qe - qa, p0, np, A, b.la, b.lb, b.lc, b.ld, i5, d_out, out_base,
@@ -1353,7 +1357,7 @@ extern "C" int f12_eval_stage(f12_quartets *q, const f12_kernel *k, int64_t q_be
   if (stage == 1) {
     const int L = bin->la + bin->lb + bin->lc + bin->ld + (i5 ? 2 : 0);
     if (launch_aux(k->d_desc.ptr, bra, ket, q->d_qb.ptr, q->d_qk.ptr, q->d_qprim.ptr, q_begin,
-                   q_end - q_begin, p0, np, L, q->d_A.ptr, st) != 0)
+                   q_end - q_begin, p0, np, L, q->d_A.ptr, st, k->host_desc.heavy) != 0)
       return F12_EDEVICE;
     q->stage_qa = q_begin;
     q->stage_qe = q_end;

@@ -13,6 +13,7 @@ constexpr int MAX_FAMILIES = 4;
 constexpr int NEG_POW_MAX = 12;        // most negative integer power of a kernel term
 constexpr int KT = 16;                  // Taylor terms of the W-table interpolation
 constexpr int KPHI = 96;                // terms of the DD Phi-series (small-T route)
+constexpr int NW_LIGHT = 32;            // the same bound for the common kernels
 constexpr int NW_MAX = 64;              // orders of W per chain in the large-T route:
                                         // (m_max - m_min) + LTOT_MAX + 1 must not exceed it
 constexpr double WX_LO = -10.5;         // W-table abscissa range
@@ -48,6 +49,7 @@ struct KernelDev {
   int32_t cls;
   int32_t nchains, nterms, nfam;
   int32_t negint;  // 1 if an integer family has negative powers (finite parts with log terms)
+  int32_t heavy;   // negint, or a chain spanning more than NW_LIGHT orders in the large-T route
   ChainDesc chains[MAX_CHAINS];
   TermDesc terms[MAX_TERMS];
   FamilyDesc fam[MAX_FAMILIES];

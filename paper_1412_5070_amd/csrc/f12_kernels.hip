@@ -83,8 +83,12 @@ __device__ double w_asym(double a, double X) {
 // H-recursion of Eq. (finalrec), which cancels like (2T)^n/(2n-1)!! in
 // binary64).  D^n(phi/R) is then formed from the R-jet of phi.
 // ---------------------------------------------------------------------------
-#define F12_NW NW_MAX
 
+// H ("heavy"): the kernel has negative integer powers (finite parts with log
+// terms) or chains whose orders span more than NW_LIGHT; a uniform property
+// of the kernel, so each launch takes one instantiation, and the common
+// kernels carry neither that code nor its larger private arrays.
+template <bool H>
 __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, int L,
                           bool do_minus, double *A) {
   double phi[LTOT_MAX + 1];
@@ -109,7 +113,7 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
     // negative integer powers: finite parts in r, Omega_{-n}(y) =
     // gam^{(n-1)/2} W_{-n}(sqrt(gam) y) - (1/2) log(gam) h_{n-1}(y), with
     // h_m(y) = [r^m] e^{-gam (r - y)^2} = gam^{m/2} e^{-X^2} Hphys_m(X) / m!
-    const bool negint = F.is_int && ch.m_min < 0;
+    const bool negint = H && F.is_int && ch.m_min < 0;
     const double hlg = negint ? 0.5 * log(gam) : 0.0;
     for (int sgn = 1; sgn >= -1; sgn -= 2) {
       if (sgn < 0 && !do_minus) break;
@@ -117,7 +121,7 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
       const double y = kap * x + cs;
       const double X = sqg * y;
       const double E = exp(e0 + a1 * x - a2 * x * x);
-      double Om[F12_NW];
+      double Om[H ? NW_MAX : NW_LIGHT];
       {
         // gam^{-(alpha0+m+1)/2} = g0 * isq^m
         double gp = g0;
@@ -152,7 +156,7 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
         }
       }
       // h_m(y), m = 0..-mlo (negative integer powers only)
-      double hh[NW_MAX + 1];
+      double hh[H ? NW_MAX + 1 : 1];
       if (negint) {
         const double eX = exp(-X * X);
         double q0 = 1.0, q1 = 2.0 * X, gpw = 1.0;
@@ -175,7 +179,7 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
         const double ct = K->terms[t].c;
         const int mt = K->terms[t].m;
         const double al = F.alpha0 + mt;
-        if (F.is_int && mt < 0) {
+        if (H && F.is_int && mt < 0) {
           // d^k/dy^k Omega_{-n} = (-1)^k (n+k-1)!/(n-1)! [Omega_{-n-k}
           //   - (sum_{j<k} 1/(n+j)) h_{n+k-1}]  (Omega'_{-n} = -n Omega_{-n-1} + h_n,
           // h_m' = -(m+1) h_{m+1})
@@ -281,13 +285,17 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
 // by-parts relation of Eq. (Srec1): 2 gam S(a+1) = a S(a-1) + b S(a)
 // (stable upward for b >= 0).  DD absorbs the exp(2T)-scale cancellation.
 // ---------------------------------------------------------------------------
-#define F12_JMAX 112
+// terms of the u-series: L + 24 + 4T, at most 112 (heavy kernels, T < 14) or
+// 64 (the others, T < 6)
+constexpr int JMAX_HEAVY = 112, JMAX_LIGHT = 64;
 
+template <bool H>
 __device__ void aux_small(const KernelDev *__restrict__ K, double xi, double u, int L, double T,
                           double *A) {
+  constexpr int JM = H ? JMAX_HEAVY : JMAX_LIGHT;
   int J = L + 24 + (int)(4.0 * T);
-  if (J > F12_JMAX) J = F12_JMAX;
-  dd M[F12_JMAX + 1];
+  if (J > JM) J = JM;
+  dd M[JM + 1];
   for (int j = 0; j <= J; ++j) M[j] = dd{0.0, 0.0};
   const int nchains = K->nchains;
   for (int c = 0; c < nchains; ++c) {
@@ -321,9 +329,9 @@ __device__ void aux_small(const KernelDev *__restrict__ K, double xi, double u, 
     //   S(-n) = gam^{(n-1)/2} Phi_{-n}(b / sqrt(gam)) - (1/2) log(gam) f_{n-1},
     // and the ladder gains + f_{-a} at every integer a <= 0 (the boundary term
     // of the integration by parts)
-    const bool negint = F.is_int && ch.m_min < 0;
+    const bool negint = H && F.is_int && ch.m_min < 0;
     const int nneg = negint ? -(ch.m_min + 1) : -1;  // -a_s
-    dd fm[NEG_POW_MAX + 2];
+    dd fm[H ? NEG_POW_MAX + 2 : 1];
     if (negint) {
       fm[0] = dd_make(1.0);
       if (nneg + 1 >= 1) fm[1] = dd_make(b);
@@ -344,7 +352,13 @@ __device__ void aux_small(const KernelDev *__restrict__ K, double xi, double u, 
         const int dk = k - off;
         if (dk >= 0 && !(dk & 1)) {
           const int j = dk >> 1;
-          if (j <= J) M[j] = dd_add(M[j], dd_mul(Sk, dd{K->terms[t].c, K->terms[t].clo}));
+          if (j <= J) {
+            // double-double coefficients where finite parts cancel between chains
+            if constexpr (H)
+              M[j] = dd_add(M[j], dd_mul(Sk, dd{K->terms[t].c, K->terms[t].clo}));
+            else
+              M[j] = dd_add(M[j], dd_mul(Sk, K->terms[t].c));
+          }
         }
       }
       // advance: S(a_s + k + 2) = ((a_s + k + 1) S(a_s + k) + b S(a_s + k + 1)) / (2 gam)
@@ -387,11 +401,13 @@ __device__ void aux_small(const KernelDev *__restrict__ K, double xi, double u, 
 // The same series in binary64, for T < 2 and L <= 5, where the cancellation
 // (about e^{2T} and the alternating u-jet product) leaves ~1e-14 of the
 // scaled envelope; the S ladders, M_j and the u-jet as in aux_small.
+template <bool H>
 __device__ void aux_small_f64(const KernelDev *__restrict__ K, double xi, double u, int L,
                               double T, double *A) {
+  constexpr int JM = H ? JMAX_HEAVY : JMAX_LIGHT;
   int J = L + 20 + (int)(4.0 * T);
-  if (J > F12_JMAX) J = F12_JMAX;
-  double M[F12_JMAX + 1];
+  if (J > JM) J = JM;
+  double M[JM + 1];
   for (int j = 0; j <= J; ++j) M[j] = 0.0;
   const int nchains = K->nchains;
   for (int c = 0; c < nchains; ++c) {
@@ -417,9 +433,9 @@ __device__ void aux_small_f64(const KernelDev *__restrict__ K, double xi, double
     }
     double Sk = p0 * f0, Snext = p1 * f1;
     // negative integer powers: finite parts as in aux_small
-    const bool negint = F.is_int && ch.m_min < 0;
+    const bool negint = H && F.is_int && ch.m_min < 0;
     const int nneg = negint ? -(ch.m_min + 1) : -1;
-    double fm[NEG_POW_MAX + 2];
+    double fm[H ? NEG_POW_MAX + 2 : 1];
     if (negint) {
       fm[0] = 1.0;
       if (nneg + 1 >= 1) fm[1] = b;
@@ -519,6 +535,7 @@ __device__ __forceinline__ int aux_bin(double T, int L, double sw) {
   return 2 + e;
 }
 
+template <bool H>
 __global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__restrict__ K, PairsDev bra,
                                                   PairsDev ket, const int64_t *__restrict__ qb,
                                                   const int64_t *__restrict__ qk,
@@ -582,12 +599,12 @@ __global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__rest
   const double T = xi * u;
   double a[LTOT_MAX + 1];
   if (T < sw) {
-    if (L <= 5 && T < 2.0 && !K->negint)
-      aux_small_f64(K, xi, u, L, T, a);
+    if (!H && L <= 5 && T < 2.0)
+      aux_small_f64<H>(K, xi, u, L, T, a);
     else
-      aux_small(K, xi, u, L, T, a);
+      aux_small<H>(K, xi, u, L, T, a);
   } else {
-    aux_large(K, xi, sqrt(u), L, minus_side_needed(T, L), a);
+    aux_large<H>(K, xi, sqrt(u), L, minus_side_needed(T, L), a);
   }
   for (int n = 0; n <= L; ++n) A[n * np + base + me] = a[n] * Np;
 }
@@ -617,11 +634,15 @@ int launch_pair_prims(int64_t npp, const int32_t *pp_sa, const int32_t *pp_sb,
 
 int launch_aux(const KernelDev *K, const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
                const int64_t *qk, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
-               int64_t np, int L, double *A, hipStream_t stream) {
+               int64_t np, int L, double *A, hipStream_t stream, int heavy) {
   if (np <= 0) return 0;
   const int64_t nbk = (np + F12_NT_AUX - 1) / F12_NT_AUX;
-  hipLaunchKernelGGL(aux_kernel, dim3((unsigned)nbk), dim3(F12_NT_AUX), 0, stream, K, bra, ket, qb, qk,
-                     qprim, qa, nqc, p0, np, L, A);
+  if (heavy)
+    hipLaunchKernelGGL(aux_kernel<true>, dim3((unsigned)nbk), dim3(F12_NT_AUX), 0, stream, K, bra, ket, qb,
+                       qk, qprim, qa, nqc, p0, np, L, A);
+  else
+    hipLaunchKernelGGL(aux_kernel<false>, dim3((unsigned)nbk), dim3(F12_NT_AUX), 0, stream, K, bra, ket, qb,
+                       qk, qprim, qa, nqc, p0, np, L, A);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -710,17 +731,36 @@ __global__ void aux_points_kernel(const KernelDev *__restrict__ K, int64_t n,
   const double Np = F12_PI52 / (sqrt(p + q) * p * q);
   double a[LTOT_MAX + 1];
   if (route == 3) {
-    aux_small_f64(K, xi, u, L, T, a);
+    aux_small_f64<true>(K, xi, u, L, T, a);
+    for (int k = 0; k <= L; ++k) A[k * n + t] = a[k] * Np;
+    return;
+  }
+  if (route == 0) {
+    // the production dispatch of aux_kernel
+    if (K->heavy) {
+      if (T < t_switch_k(K, L))
+        aux_small<true>(K, xi, u, L, T, a);
+      else
+        aux_large<true>(K, xi, R, L, minus_side_needed(T, L), a);
+    } else {
+      if (T < t_switch_k(K, L)) {
+        if (L <= 5 && T < 2.0)
+          aux_small_f64<false>(K, xi, u, L, T, a);
+        else
+          aux_small<false>(K, xi, u, L, T, a);
+      } else {
+        aux_large<false>(K, xi, R, L, minus_side_needed(T, L), a);
+      }
+    }
     for (int k = 0; k <= L; ++k) A[k * n + t] = a[k] * Np;
     return;
   }
   const bool small = (route == 1) || (route == 0 && T < t_switch_k(K, L));
-  if (small && route == 0 && L <= 5 && T < 2.0 && !K->negint)
-    aux_small_f64(K, xi, u, L, T, a);
-  else if (small)
-    aux_small(K, xi, u, L, T, a);
+  // routes 1, 2: one formula forced, with the large arrays
+  if (small)
+    aux_small<true>(K, xi, u, L, T, a);
   else
-    aux_large(K, xi, R, L, route == 2 ? true : minus_side_needed(T, L), a);
+    aux_large<true>(K, xi, R, L, true, a);
   for (int k = 0; k <= L; ++k) A[k * n + t] = a[k] * Np;
 }
 

@@ -14,7 +14,7 @@ int launch_pair_prims(int64_t npp, const int32_t *pp_sa, const int32_t *pp_sb,
 
 int launch_aux(const KernelDev *K, const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
                const int64_t *qk, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
-               int64_t np, int L, double *A, hipStream_t stream);
+               int64_t np, int L, double *A, hipStream_t stream, int heavy);
 
 int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb, const int64_t *qk,
                     const int64_t *qoff, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
