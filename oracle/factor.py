@@ -27,6 +27,15 @@ class Factor:
     n: int = 0
 
 
+@dataclass(frozen=True)
+class TermFactor:
+    """A factor given by its terms, f(r) = sum_t c_t r^alpha_t exp(b_t r - g_t r^2):
+    the same family of functions that Eq. (rs12) expands into, for other
+    correlation factors (Gaussian geminals, their products with powers of r).
+    terms: tuple of (c, alpha, b, g)."""
+    terms: tuple
+
+
 def tang_toennies(n, x):
     """S_n(x) of Eq. (ttdamp) in DD for DD x >= 0.
 
@@ -58,9 +67,23 @@ def tang_toennies(n, x):
     return dd.where(small_mask, small, big)
 
 
+def _terms_value(fac, r, deriv):
+    """sum_t c_t r^alpha_t e^{b_t r - g_t r^2} (or its r-derivative) in DD."""
+    out = dd.zeros(r.shape)
+    lr = dd.log(r)
+    for (c, a, b, g) in fac.terms:
+        e = dd.exp(lr * float(a) + r * float(b) - r * r * float(g))
+        if deriv:
+            e = e * (float(a) / r + float(b) - 2.0 * float(g) * r)
+        out = out + e * float(c)
+    return out
+
+
 def f_value(fac, r):
-    """f(r) of Eq. (rs12) in DD."""
+    """f(r) of Eq. (rs12) in DD (or of a TermFactor)."""
     r = dd.DD(r)
+    if isinstance(fac, TermFactor):
+        return _terms_value(fac, r, False)
     mr2 = fac.mu * r * r
     g = dd.exp(-mr2)
     short = (1.0 + 0.5 * r) * g
@@ -78,6 +101,8 @@ def f_deriv(fac, r):
     (mu r^2)^n / n!; and d/dr[r^rho e^{B r}] = (rho/r + B) r^rho e^{B r}.
     """
     r = dd.DD(r)
+    if isinstance(fac, TermFactor):
+        return _terms_value(fac, r, True)
     mr2 = fac.mu * r * r
     g = dd.exp(-mr2)
     short = (0.5 - 2.0 * fac.mu * r - fac.mu * r * r) * g
@@ -105,8 +130,35 @@ def kernel_times_r(cls, fac, facp, r):
     raise ValueError(f"class {cls} has no kernel of its own (I5 is built from I3)")
 
 
+def _growth(fac):
+    if isinstance(fac, TermFactor):
+        return max([0.0] + [float(b) for (c, a, b, g) in fac.terms if g == 0 and b > 0])
+    return max(fac.B, 0.0) if fac.c0 != 0 else 0.0
+
+
+def gaussian_rates(cls, fac, facp):
+    """Gaussian exponents mu of the kernel's geminal parts (used to place
+    quadrature panels around their peaks)."""
+    def rates(f):
+        if isinstance(f, TermFactor):
+            return sorted({float(g) for (c, a, b, g) in f.terms if g > 0})
+        return [f.mu]
+    if cls in (2, 3):
+        return rates(fac)
+    if cls in (4, 6):
+        r1, r2 = rates(fac), rates(facp)
+        return sorted({a + b for a in r1 for b in r2} | set(r1) | set(r2))
+    return [0.0]
+
+
 def growth_rate(cls, fac, facp):
     """Largest exponential growth rate b of K_i (used to place quadrature panels)."""
+    if isinstance(fac, TermFactor) or isinstance(facp, TermFactor):
+        if cls in (2, 3):
+            return _growth(fac)
+        if cls in (4, 6):
+            return _growth(fac) + _growth(facp)
+        return 0.0
     b = 0.0
     if cls in (2, 3):
         b = max(fac.B, 0.0) if fac.c0 != 0 else 0.0

@@ -30,9 +30,40 @@ import math
 import numpy as np
 from . import dd
 from .quadrature import gauss_legendre, tanh_sinh
-from .factor import kernel_times_r, growth_rate
+from .factor import TermFactor, gaussian_rates, growth_rate, kernel_times_r
 
-N_PANELS = 16
+N_PEAK = 8  # Gauss-Legendre panels across each peak of the integrand
+
+
+def _interior_edges(xi, R, lo, hi, c, w, b, mus):
+    """Panel edges inside [lo, hi] (arrays over quartets, shape (P, M)).
+
+    The integrand has up to two kinds of peaks: the pair Gaussian shifted by
+    the kernel's growth, centred at c with width w = xi^-1/2 (14 widths each
+    side), and, for each Gaussian rate mu of the kernel, the product of two
+    Gaussians centred at r* = xi R / (mu + xi) (up to b / (2 (mu + xi)) further
+    out for terms that also grow) with width (mu + xi)^-1/2 (12 widths each
+    side).  Each peak gets N_PEAK panels of its own: a kernel much narrower
+    than the pair Gaussian (mu >> xi) puts all its weight in a region far
+    smaller than R, which a subdivision of [lo, hi] into equal panels would
+    resolve poorly.  Edges are clipped to [lo, hi] and sorted; the gaps
+    between peaks are single panels (the integrand there is below exp(-144)
+    of its peaks)."""
+    cand = [lo + 0.0 * xi, hi + 0.0 * xi]
+    for k in range(N_PEAK + 1):
+        cand.append(c - 14.0 * w + 28.0 * w * k / N_PEAK)
+    for mu in mus:
+        if mu > 0:
+            sig = 1.0 / np.sqrt(mu + xi)
+            rstar = xi * R / (mu + xi)
+            a = rstar - 12.0 * sig
+            e = rstar + b / (2.0 * (mu + xi)) + 12.0 * sig
+            for k in range(N_PEAK + 1):
+                cand.append(a + (e - a) * k / N_PEAK)
+    E = np.stack(cand, axis=1)
+    E = np.clip(E, lo[:, None], hi[:, None])
+    E.sort(axis=1)
+    return E
 
 
 def _nodes(xi, R, cls, fac, facp):
@@ -41,11 +72,7 @@ def _nodes(xi, R, cls, fac, facp):
     R = np.asarray(R, float)
     w = 1.0 / np.sqrt(xi)
     b = growth_rate(cls, fac, facp)
-    mus = [0.0]
-    if cls in (2, 3):
-        mus = [fac.mu]
-    elif cls in (4, 6):
-        mus = [fac.mu + facp.mu, fac.mu, facp.mu]
+    mus = gaussian_rates(cls, fac, facp)
     c = R + b / (2.0 * xi)
     a1 = 0.5 * np.minimum(w, 1.0)
     hi = c + 14.0 * w
@@ -74,9 +101,9 @@ def _nodes(xi, R, cls, fac, facp):
     rr, ww = gl_panel(a1, lo)
     parts_r.append(rr)
     parts_w.append(ww)
-    edges = [lo + (hi - lo) * k / N_PANELS for k in range(N_PANELS + 1)]
-    for k in range(N_PANELS):
-        rr, ww = gl_panel(edges[k], edges[k + 1])
+    E = _interior_edges(xi, R, lo, hi, c, w, b, mus)
+    for k in range(E.shape[1] - 1):
+        rr, ww = gl_panel(E[:, k], E[:, k + 1])
         parts_r.append(rr)
         parts_w.append(ww)
     r = dd.DD(np.concatenate([p.hi for p in parts_r], 1), np.concatenate([p.lo for p in parts_r], 1))
@@ -245,7 +272,16 @@ def _kernel_mp(cls, fac, facp, r):
             head += t
         return 1 - mp.exp(-x) * head
 
+    def terms(fc, deriv):
+        v = mp.mpf(0)
+        for (c, a, b, g) in fc.terms:
+            e = mp.power(r, a) * mp.exp(b * r - g * r * r)
+            v += c * (e * (a / r + b - 2 * g * r) if deriv else e)
+        return v
+
     def f(fc):
+        if isinstance(fc, TermFactor):
+            return terms(fc, False)
         g = mp.exp(-fc.mu * r * r)
         v = (1 + r / 2) * g
         if fc.c0 != 0:
@@ -253,6 +289,8 @@ def _kernel_mp(cls, fac, facp, r):
         return v
 
     def fr(fc):
+        if isinstance(fc, TermFactor):
+            return terms(fc, True)
         mr2 = fc.mu * r * r
         g = mp.exp(-mr2)
         v = (mp.mpf(1) / 2 - 2 * fc.mu * r - fc.mu * r * r) * g
@@ -292,11 +330,7 @@ def radial_derivatives_mp(cls, xi, R, nmax, fac, facp, extra_digits=None):
         a1 = min(w, mp.mpf(1)) / 2
         hi = c + 14 * w
         lo = c - 14 * w
-        mus = [0.0]
-        if cls in (2, 3):
-            mus = [fac.mu]
-        elif cls in (4, 6):
-            mus = [fac.mu + facp.mu, fac.mu, facp.mu]
+        mus = gaussian_rates(cls, fac, facp)
         for mu in mus:
             if mu > 0:
                 rstar = xi_m * R_m / (mu + xi_m)
@@ -317,8 +351,13 @@ def radial_derivatives_mp(cls, xi, R, nmax, fac, facp, extra_digits=None):
         hstep = mp.mpf(2) ** (-tlev)
         tnodes = [(x, w * hstep) for (x, w) in tnodes]
         pts = [(mp.mpf(0), a1, tnodes), (a1, lo, gnodes)]
-        edges = [lo + (hi - lo) * k / N_PANELS for k in range(N_PANELS + 1)]
-        pts += [(edges[k], edges[k + 1], gnodes) for k in range(N_PANELS)]
+        # interior edges from the binary64 placement; the ends stay exact
+        Ef = _interior_edges(np.array([float(xi_m)]), np.array([float(R_m)]), np.array([float(lo)]),
+                             np.array([float(hi)]), np.array([float(c)]), np.array([float(w)]), float(b),
+                             mus)[0]
+        edges = [lo] + [mp.mpf(float(v)) for v in Ef[1:-1]] + [hi]
+        edges = [min(max(v, lo), hi) for v in edges]
+        pts += [(edges[k], edges[k + 1], gnodes) for k in range(len(edges) - 1)]
         acc = [mp.mpf(0)] * (nmax + 1)
         kmax = 2 * nmax + 1
         for (x0, x1, nodes) in pts:

@@ -34,6 +34,16 @@ FACTOR_SETS = {
 }
 
 
+# A correlation factor given by terms c r^alpha exp(b r - g r^2) instead of the
+# range-separated parameters: three Gaussian geminals (the form of the usual
+# Gaussian fits of an exponential correlation factor), a half-integer power
+# and a growing term, so that every family of the term path is exercised.
+GENERIC_FACTORS = {
+    "G5": ((0.3, 0.0, 0.0, 0.2), (0.5, 0.0, 0.0, 1.1), (0.2, 0.0, 0.0, 5.0),
+           (0.1, 1.0, 0.4, 0.7), (0.05, 0.5, 0.0, 0.9)),
+}
+
+
 @dataclass
 class Shell:
     center: np.ndarray

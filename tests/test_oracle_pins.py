@@ -101,6 +101,33 @@ def test_radial_geminal_closed_form(xi, T):
             assert abs(A[0, n] - ref) <= 1e-20 * abs(ref) + 1e-28, (n, A[0, n], ref)
 
 
+@pytest.mark.parametrize("mu", [5.0, 50.0])
+@pytest.mark.parametrize("xi,T", [(0.0135, 600.0), (0.013, 400.0), (0.0157, 107.0), (0.3, 200.0)])
+def test_radial_narrow_geminal_closed_form(mu, xi, T):
+    """Kernels much narrower than the pair Gaussian (mu >> xi) at large T put
+    all the weight of the r-integral near r* = xi R / (mu + xi), far below R:
+    the quadrature must resolve that peak on its own.  Closed forms (textbook
+    Gaussian products, u = R^2): for e^{-mu r^2},
+      B/(pi/(p+q))^{3/2} = (pi/(mu+xi))^{3/2} e^{-w u},  w = mu xi/(mu+xi),
+    so A_n = (-2w)^n B exactly; for e^{-mu r^2}/r the F_0 form above."""
+    from oracle.factor import TermFactor
+    nmax = 3
+    R = math.sqrt(T / xi)
+    G = TermFactor(((1.0, 0.0, 0.0, mu),))
+    A3 = radial.radial_auto(3, [xi], [R], nmax, G, G).to_mp()
+    A2 = radial.radial_auto(2, [xi], [R], 0, G, G).to_mp()
+    with mp.workdps(50):
+        scale = mp.mpf(xi) / mp.pi
+        m, x, u = mp.mpf(mu), mp.mpf(xi), mp.mpf(R) ** 2
+        w = m * x / (m + x)
+        b3 = (mp.pi / (m + x)) ** 1.5 * mp.exp(-w * u) * scale
+        for n in range(nmax + 1):
+            ref = (-2 * w) ** n * b3
+            assert abs(A3[0, n] - ref) <= 1e-20 * abs(ref), (n, A3[0, n], ref)
+        ref2 = 2 * mp.pi / (m + x) * mp.exp(-w * u) * boys(0, x * x * u / (m + x)) * scale
+        assert abs(A2[0, 0] - ref2) <= 1e-20 * abs(ref2), (A2[0, 0], ref2)
+
+
 def test_bfinal_vs_3d_convolution():
     """Eq. (bfinal) against the 2-D integral it comes from: B = (pi/(p+q))^{3/2}
     int d^3v k3(|v|) exp(-xi |v - X|^2), done in (v, cos theta) with mpmath."""

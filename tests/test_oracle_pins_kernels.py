@@ -16,14 +16,18 @@ import numpy as np
 import pytest
 
 from oracle import dd, integrals, radial
-from oracle.factor import f_deriv, f_value
-from synth import FACTOR_SETS
+from oracle.factor import TermFactor, f_deriv, f_value
+from synth import FACTOR_SETS, GENERIC_FACTORS
 
 P1, P2, P3, P4 = (FACTOR_SETS[k] for k in ("P1", "P2", "P3", "P4"))
 
 
 def _f_mp(fac):
-    """f(r) of Eq. (rs12) with S_n of Eq. (ttdamp), in mpmath (working precision)."""
+    """f(r) of Eq. (rs12) with S_n of Eq. (ttdamp), in mpmath (working
+    precision), or the sum of the terms of a TermFactor."""
+    if isinstance(fac, TermFactor):
+        return lambda r: mp.fsum(mp.mpf(c) * mp.power(r, a) * mp.exp(b * r - g * r * r) for (c, a, b, g) in fac.terms)
+
     def f(r):
         x = fac.mu * r * r
         head, t = mp.mpf(1), mp.mpf(1)
@@ -106,7 +110,8 @@ def _convolution_derivatives(cls, fac, facp, xi, R, nmax=3):
         cache[v] = acc
         return acc
 
-    peak = R + max(fac.B, 0) / xi
+    B = max([0.0] + [b for (c, a, b, g) in fac.terms if b > 0]) if isinstance(fac, TermFactor) else max(fac.B, 0)
+    peak = R + B / xi
     w = 1 / mp.sqrt(xi)
     pts = [0, max(peak - 8 * w, 0) / 2, max(peak - 8 * w, mp.mpf("0.01")), peak, peak + 8 * w, peak + 30 * w]
     pts = sorted(set(pts))
@@ -119,16 +124,20 @@ def _convolution_derivatives(cls, fac, facp, xi, R, nmax=3):
 
 @pytest.mark.parametrize("cls,fa,fb,T", [(2, "P1", "P1", 5.0), (4, "P1", "P4", 0.3), (4, "P4", "P4", 40.0),
                                          (6, "P1", "P1", 5.0), (4, "P2", "P2", 0.3), (2, "P3", "P3", 5.0),
-                                         (6, "P1", "P4", 40.0), (3, "P3", "P3", 40.0)])
+                                         (6, "P1", "P4", 40.0), (3, "P3", "P3", 40.0), (2, "G5", "G5", 5.0),
+                                         (6, "G5", "G5", 0.3)])
 def test_geminal_kernels_vs_convolution_quadrature(cls, fa, fb, T):
     """(ss|k_i|ss) radial derivatives n = 0..3 of the oracle (Eq. (bfinal) by
     its own panels and derivative forms) against the two-dimensional
     convolution quadrature above, for kernels with a long-range part
     (c0 != 0): I2, I4 with (P1, P4) and (P4, P4), I6, and the negative powers
-    of P2 in I4 (rho + rho' = -3) and of P3 in I2 and I3.  Catches a wrong
+    of P2 in I4 (rho + rho' = -3) and of P3 in I2 and I3, and a factor given
+    by its terms (G5: Gaussian geminals, a half-integer power, a growing term).  Catches a wrong
     r k_i(r) for I4/I6 with c0 != 0 and quadrature panels placed without the
     exp((B + B') r) growth, which symmetry and invariance tests cannot see."""
-    fac, facp = FACTOR_SETS[fa], FACTOR_SETS[fb]
+    def get(name):
+        return TermFactor(GENERIC_FACTORS[name]) if name in GENERIC_FACTORS else FACTOR_SETS[name]
+    fac, facp = get(fa), get(fb)
     xi = 0.9
     R = math.sqrt(T / xi)
     A = radial.radial_auto(cls, [xi], [R], 3, fac, facp).to_mp()[0]
