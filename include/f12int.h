@@ -113,6 +113,20 @@ void f12_pairs_destroy(f12_pairs *pairs);
  * W_a(x) = R int_0^inf t^a exp(-(t-x)^2) dt (Eq. (sila) with gamma = 1) for the
  * chains' alpha families; uploads everything to the current device. */
 int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_factor *fp, f12_kernel **out);
+/* Kernel of class `cls` for factors given by their terms instead of the
+ * parameters of Eq. (rs12): f(r) = sum_t c_t r^alpha_t exp(b_t r - g_t r^2)
+ * (f_terms: host double[4 nf] of (c, alpha, b, g); the same for f' with
+ * nfp = 0 and fp_terms = NULL meaning f' = f; f' is used by I4 and I6).  Any
+ * such factor goes through the same term tables and kernels as Eq. (rs12):
+ * Gaussian geminals sum_i c_i exp(-g_i r^2) (the Gaussian fits of Ten-no's
+ * exponential), their products with powers of r, growing or bounded
+ * exponentials.  The kernels k_i are formed from f as for Eq. (rs12):
+ * I2 f/r, I3 and I5 f, I4 f f', I6 f_r f'_r.  Each term needs g >= 0,
+ * b >= 0 and either an integer alpha >= 0 or a non-integer alpha > -1
+ * (else F12_EPARAM; a decaying exponential, b < 0, is not supported);
+ * 1 <= nf <= 96 (else F12_EINVAL). */
+int f12_kernel_create_terms(int32_t cls, int32_t nf, const double *f_terms, int32_t nfp,
+                            const double *fp_terms, f12_kernel **out);
 /* Copies up to `cap` terms as (c, alpha, b, g) quadruples into out[4*k..]. */
 int f12_kernel_terms(const f12_kernel *k, int32_t *nterms, double *out, int32_t cap);
 void f12_kernel_destroy(f12_kernel *k);

@@ -658,6 +658,10 @@ extern "C" int f12_aux_w_column(double alpha0, int32_t is_int, int32_t m_lo, int
   return F12_OK;
 }
 
+namespace {
+int kernel_from_factors(int32_t cls, const Expr &ef, const Expr &efp, f12_kernel **out);
+}  // namespace
+
 extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_factor *fp,
                                  f12_kernel **out) {
   if (!out) return F12_EINVAL;
@@ -672,17 +676,55 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
     int s = validate_factor(fp);
     if (s) return s;
   }
+  Expr ef, efp;
+  if (cls != 1) ef = factor_expr(*f);
+  if (cls == 4 || cls == 6) efp = factor_expr(*fp);
+  return kernel_from_factors(cls, ef, efp, out);
+}
+
+extern "C" int f12_kernel_create_terms(int32_t cls, int32_t nf, const double *f_terms, int32_t nfp,
+                                       const double *fp_terms, f12_kernel **out) {
+  if (!out) return F12_EINVAL;
+  *out = nullptr;
+  if (cls < 1 || cls > 6) return F12_EINVAL;
+  auto read = [](int32_t n, const double *t, Expr &e) -> int {
+    if (n <= 0 || n > MAX_TERMS || !t) return F12_EINVAL;
+    for (int i = 0; i < n; ++i) {
+      const double c = t[4 * i], a = t[4 * i + 1], b = t[4 * i + 2], g = t[4 * i + 3];
+      if (!std::isfinite(c) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(g)) return F12_EPARAM;
+      if (g < 0.0 || b < 0.0) return F12_EPARAM;
+      const bool integer = a == std::floor(a);
+      if ((integer && a < 0.0) || (!integer && a <= -1.0)) return F12_EPARAM;
+      add_term(e, {c, a, b, g});
+    }
+    return F12_OK;
+  };
+  Expr ef, efp;
+  if (cls != 1) {
+    int s = read(nf, f_terms, ef);
+    if (s) return s;
+  }
+  if (cls == 4 || cls == 6) {
+    int s = (nfp == 0 && !fp_terms) ? F12_OK : read(nfp, fp_terms, efp);
+    if (s) return s;
+    if (nfp == 0 && !fp_terms) efp = ef;
+  }
+  return kernel_from_factors(cls, ef, efp, out);
+}
+
+namespace {
+int kernel_from_factors(int32_t cls, const Expr &ef, const Expr &efp, f12_kernel **out) {
   std::unique_ptr<f12_kernel> K(new (std::nothrow) f12_kernel);
   if (!K) return F12_ENOMEM;
   K->cls = cls;
   Expr e;
   switch (cls) {
     case 1: add_term(e, {1.0, 0.0, 0.0, 0.0}); break;
-    case 2: e = factor_expr(*f); break;
+    case 2: e = ef; break;
     case 3:
-    case 5: e = shift_alpha(factor_expr(*f), 1.0); break;
-    case 4: e = shift_alpha(mul(factor_expr(*f), factor_expr(*fp)), 1.0); break;
-    case 6: e = shift_alpha(mul(deriv(factor_expr(*f)), deriv(factor_expr(*fp))), 1.0); break;
+    case 5: e = shift_alpha(ef, 1.0); break;
+    case 4: e = shift_alpha(mul(ef, efp), 1.0); break;
+    case 6: e = shift_alpha(mul(deriv(ef), deriv(efp)), 1.0); break;
   }
   // drop exact cancellations
   Expr e2;
@@ -764,6 +806,9 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
   D.nterms = nt;
   D.negint = 0;
   D.heavy = 0;
+  D.singular = 0;
+  for (int c = 0; c < D.nchains; ++c)
+    if (fams[D.chains[c].family].a0 + D.chains[c].m_min <= -1.0 + 1e-9) D.singular = 1;
   for (int c = 0; c < D.nchains; ++c) {
     if (fams[D.chains[c].family].is_int && D.chains[c].m_min < 0) D.negint = 1;
     if (D.chains[c].m_max - D.chains[c].m_min + LTOT_MAX + 1 > NW_LIGHT) D.heavy = 1;
@@ -836,6 +881,7 @@ extern "C" int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_fac
   *out = K.release();
   return F12_OK;
 }
+}  // namespace
 
 extern "C" int f12_kernel_terms(const f12_kernel *k, int32_t *nterms, double *out, int32_t cap) {
   if (!k || !nterms) return F12_EINVAL;

@@ -90,10 +90,16 @@ __device__ double w_asym(double a, double X) {
 // kernels carry neither that code nor its larger private arrays.
 template <bool H>
 __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, int L,
-                          bool do_minus, double *A) {
+                          double mbudget, double *A) {
   double phi[LTOT_MAX + 1];
   for (int m = 0; m <= L; ++m) phi[m] = 0.0;
   const int nchains = K->nchains;
+  // minus sides: per chain, or, for a kernel with finite parts, for every
+  // chain once any needs it (the pieces at r ~ 0 cancel only across chains)
+  const double T = xi * R * R;
+  bool any_minus = false;
+  if (K->singular)
+    for (int c = 0; c < nchains; ++c) any_minus |= T * (xi / (xi + K->chains[c].g)) < mbudget;
   for (int c = 0; c < nchains; ++c) {
     const ChainDesc ch = K->chains[c];
     const FamilyDesc F = K->fam[ch.family];
@@ -115,11 +121,13 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
     // h_m(y) = [r^m] e^{-gam (r - y)^2} = gam^{m/2} e^{-X^2} Hphys_m(X) / m!
     const bool negint = H && F.is_int && ch.m_min < 0;
     const double hlg = negint ? 0.5 * log(gam) : 0.0;
+    const bool do_minus = K->singular ? any_minus : kap * T < mbudget;
     for (int sgn = 1; sgn >= -1; sgn -= 2) {
       if (sgn < 0 && !do_minus) break;
       const double x = sgn * R;
       const double y = kap * x + cs;
       const double X = sqg * y;
+      if (sgn < 0 && X < WX_LO) break;  // below exp(-110) of this chain's F(R)
       const double E = exp(e0 + a1 * x - a2 * x * x);
       double Om[H ? NW_MAX : NW_LIGHT];
       {
@@ -505,14 +513,24 @@ __device__ __forceinline__ double t_switch_k(const KernelDev *K, int L) {
   return (K->negint && sw < TSW_NEGINT) ? TSW_NEGINT : sw;
 }
 
-__device__ __forceinline__ bool minus_side_needed(double T, int L) {
-  // keep the F(-R) branch while exp(-T) (2T)^L / (2L-1)!! > 1e-19
-  double lg = -T;
+// The F(-R) side of the large-T route.  Against F(R) of its own chain it is
+// damped by exp(-kappa T - b kappa R - b^2/(4 gam)) <= exp(-kappa T),
+// kappa = xi / (xi + g): the far side of the pair Gaussian meets the kernel
+// at r ~ 0, the near side at r ~ kappa R.  For g = 0 (kappa = 1) the plus
+// side's A_n can fall like (2n-1)!!/(2T)^n, so a chain keeps its minus side
+// while exp(-kappa T) (2T)^L / (2L-1)!! > 1e-19, i.e. kappa T < minus_budget;
+// and never where the minus-side argument lies below the W tables, where the
+// side is below exp(-110) of its plus side.  Terms r^a with a <= -1 are
+// finite parts: a chain's side then holds pieces of size exp(-T) (2 xi R)^k
+// from r ~ 0 that cancel only in the sum over chains, so such a kernel takes
+// the minus side of every chain or of none.
+__device__ __forceinline__ double minus_budget(double T, int L) {
+  double lg = 43.7;
   if (L > 0) {
     lg += L * log(2.0 * T);
     for (int k = 3; k <= 2 * L - 1; k += 2) lg -= log((double)k);
   }
-  return lg > -43.7 && T < 108.0;
+  return lg;
 }
 
 // ---------------------------------------------------------------------------
@@ -604,7 +622,7 @@ __global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__rest
     else
       aux_small<H>(K, xi, u, L, T, a);
   } else {
-    aux_large<H>(K, xi, sqrt(u), L, minus_side_needed(T, L), a);
+    aux_large<H>(K, xi, sqrt(u), L, minus_budget(T, L), a);
   }
   for (int n = 0; n <= L; ++n) A[n * np + base + me] = a[n] * Np;
 }
@@ -741,7 +759,7 @@ __global__ void aux_points_kernel(const KernelDev *__restrict__ K, int64_t n,
       if (T < t_switch_k(K, L))
         aux_small<true>(K, xi, u, L, T, a);
       else
-        aux_large<true>(K, xi, R, L, minus_side_needed(T, L), a);
+        aux_large<true>(K, xi, R, L, minus_budget(T, L), a);
     } else {
       if (T < t_switch_k(K, L)) {
         if (L <= 5 && T < 2.0)
@@ -749,7 +767,7 @@ __global__ void aux_points_kernel(const KernelDev *__restrict__ K, int64_t n,
         else
           aux_small<false>(K, xi, u, L, T, a);
       } else {
-        aux_large<false>(K, xi, R, L, minus_side_needed(T, L), a);
+        aux_large<false>(K, xi, R, L, minus_budget(T, L), a);
       }
     }
     for (int k = 0; k <= L; ++k) A[k * n + t] = a[k] * Np;
@@ -760,7 +778,7 @@ __global__ void aux_points_kernel(const KernelDev *__restrict__ K, int64_t n,
   if (small)
     aux_small<true>(K, xi, u, L, T, a);
   else
-    aux_large<true>(K, xi, R, L, true, a);
+    aux_large<true>(K, xi, R, L, 1e300, a);
   for (int k = 0; k <= L; ++k) A[k * n + t] = a[k] * Np;
 }
 

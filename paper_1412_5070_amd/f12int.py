@@ -44,6 +44,7 @@ EXPORTS = {
     "f12_pairs_count": (_c_i32, [_vp, _P(_c_i64), _P(_c_i64)]),
     "f12_pairs_destroy": (None, [_vp]),
     "f12_kernel_create": (_c_i32, [_c_i32, _P(Factor), _P(Factor), _P(_vp)]),
+    "f12_kernel_create_terms": (_c_i32, [_c_i32, _c_i32, _P(_c_dbl), _c_i32, _P(_c_dbl), _P(_vp)]),
     "f12_kernel_terms": (_c_i32, [_vp, _P(_c_i32), _P(_c_dbl), _c_i32]),
     "f12_kernel_destroy": (None, [_vp]),
     "f12_quartets_build": (_c_i32, [_vp, _vp, _c_i32, _c_dbl, _vp, _vp, _P(_vp), _P(_c_i64), _P(_c_i64)]),
@@ -154,6 +155,20 @@ class Kernel:
         fpc = Factor.of(fp) if fp is not None else None
         _check(_lib.f12_kernel_create(self.cls, ctypes.byref(fc), ctypes.byref(fpc) if fpc else None,
                                       ctypes.byref(self.handle)), "f12_kernel_create")
+
+    @staticmethod
+    def from_terms(cls, f_terms, fp_terms=None):
+        """f12_kernel_create_terms: factors given as (c, alpha, b, g) rows of
+        f(r) = sum c r^alpha exp(b r - g r^2)."""
+        k = Kernel.__new__(Kernel)
+        k.cls = int(cls)
+        k.handle = _vp()
+        ft = np.ascontiguousarray(f_terms, dtype=np.float64).reshape(-1, 4)
+        fpt = None if fp_terms is None else np.ascontiguousarray(fp_terms, dtype=np.float64).reshape(-1, 4)
+        _check(_lib.f12_kernel_create_terms(k.cls, len(ft), _dptr(ft), 0 if fpt is None else len(fpt),
+                                            None if fpt is None else _dptr(fpt), ctypes.byref(k.handle)),
+               "f12_kernel_create_terms")
+        return k
 
     def terms(self):
         n = _c_i32()

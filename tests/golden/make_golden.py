@@ -28,6 +28,8 @@ Sets:
   negpow   the 3-atom s+p molecule with kernels that have negative integer
            powers: P3 (rho = -3, n = 2) in I2-I6, P2 in I4/I6 (rho + rho' = -3),
            and the mixed pairs (P1, P3), (P3, P1); I3 beside the I5 entries.
+  generic  the 3-atom s+p molecule with the factor G5 given by its terms
+           (synth.GENERIC_FACTORS): I2-I6.
   factors  the 3-atom s+p molecule (seed 1412) with the other factor sets:
            P2 (non-integer rho < -1) for I2, I3, I5; P4 (integer rho >= 0)
            for I2-I6; the mixed pair (f, f') = (P1, P4) for I4 and I6; I3
@@ -167,6 +169,12 @@ def factor_key(cls, f, fp, quad):
 
 def _job(args):
     setname, cls, quad = args[:3]
+    if setname == "generic":
+        from oracle.factor import TermFactor
+        from synth import GENERIC_FACTORS, tiny_config
+        G = TermFactor(GENERIC_FACTORS[args[3]])
+        sh = [tiny_config()[1][i].as_dict() for i in quad]
+        return args, np.asarray(integrals.contracted(cls, *sh, G, G), dtype=np.float64).ravel()
     if setname in ("factors", "negpow"):
         from synth import tiny_config
         f, fp = args[3], args[4]
@@ -201,6 +209,8 @@ def build(setname):
         from synth import config_precision
         quads = prec35_quads()
         jobs = [(setname, c, q) for c in (5, 2, 3, 4, 6) for q in quads]
+    elif setname == "generic":
+        jobs = [(setname, c, q, "G5", "G5") for c in (5, 2, 3, 4, 6) for q in FACTOR_QUADS]
     elif setname in ("factors", "negpow"):
         base = FACTOR_CASES if setname == "factors" else NEGPOW_CASES
         cases = list(base) + [(3, f, fp) for (c, f, fp) in base if c == 5 and (3, f, fp) not in base]
@@ -212,7 +222,7 @@ def build(setname):
     with Pool(int(os.environ.get("GOLDEN_PROCS", "6"))) as pool:
         for args, val in pool.imap_unordered(_job, jobs):
             sname, cls, quad = args[:3]
-            if sname in ("factors", "negpow"):
+            if sname in ("factors", "negpow", "generic"):
                 out[factor_key(cls, args[3], args[4], quad)] = val
             else:
                 out["c%d_%d_%d_%d_%d" % ((cls,) + tuple(quad))] = val

@@ -151,3 +151,19 @@ def test_unsupported_kernel_terms_rejected_before_device():
         with pytest.raises(f12int.F12Error) as e:
             f12int.Kernel(cls, f, f)
         assert e.value.status == -2
+
+
+def test_factor_terms_validation_before_device():
+    """f12_kernel_create_terms rejects, before any device work, terms it does
+    not evaluate (a decaying exponential b < 0, a negative Gaussian exponent,
+    a negative integer or a non-integer power <= -1, non-finite values) and
+    malformed lists."""
+    from paper_1412_5070_amd import f12int
+    for bad in ([[1.0, 0.0, -0.5, 0.0]], [[1.0, 0.0, 0.0, -1.0]], [[1.0, -1.0, 0.0, 1.0]],
+                [[1.0, -1.5, 0.0, 1.0]], [[np.nan, 0.0, 0.0, 1.0]]):
+        with pytest.raises(f12int.F12Error) as e:
+            f12int.Kernel.from_terms(3, bad)
+        assert e.value.status == -2, bad
+    with pytest.raises(f12int.F12Error) as e:
+        f12int.Kernel.from_terms(3, np.zeros((0, 4)))
+    assert e.value.status == -1

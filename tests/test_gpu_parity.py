@@ -364,6 +364,86 @@ def test_factor_sets_vs_golden(lib, cls, f, fp):
         assert e < REL_TOL, (qd, e)
 
 
+@pytest.mark.parametrize("cls", [2, 3, 4, 6, 5])
+def test_factor_from_terms_vs_golden(lib, cls):
+    """A correlation factor given by its terms (f12_kernel_create_terms; G5:
+    Gaussian geminals, a half-integer power and a growing term) on the 3-atom
+    s+p molecule against stored oracle values, and its radial derivatives
+    against the live oracle at L = 4 and 12."""
+    import os
+    from oracle import radial
+    from oracle.factor import TermFactor
+    from synth import GENERIC_FACTORS
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import FACTOR_QUADS, factor_key
+    golden = _golden("generic")
+    shells = _tiny()
+    basis = lib.Basis.from_shells(shells)
+    pairs = lib.Pairs(basis, 1)
+    terms = np.array(GENERIC_FACTORS["G5"])
+    k = lib.Kernel.from_terms(cls, terms, terms)
+    got = run_quads(lib, basis, pairs, k, cls, FACTOR_QUADS)
+    print(f"generic G5 cls={cls}", flush=True)
+    for qd in FACTOR_QUADS:
+        ref = golden[factor_key(cls, "G5", "G5", qd)]
+        if cls == 5:
+            ref3 = golden[factor_key(3, "G5", "G5", qd)]
+            e = i5_block_err(got[qd], ref, ref3, np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps]),
+                             i5_vanishes(shells[qd[0]].l, qd[0] == qd[1]))
+        else:
+            e = block_rel_err(got[qd], ref)
+        print(f"  {qd} max|I| {np.max(np.abs(ref)):.1e} err {e:.2e}", flush=True)
+        assert e < REL_TOL, (qd, e)
+    if cls == 5:
+        return
+    G = TermFactor(GENERIC_FACTORS["G5"])
+    pts = _radial_points()
+    p = np.array([x[0] for x in pts]); q = np.array([x[1] for x in pts]); R = np.array([x[2] for x in pts])
+    xi = p * q / (p + q)
+    for L in (4, 12):
+        keep = np.array([radial.cancellation_digits(t, L) < 13 for t in xi * R * R])
+        A = lib.aux_radial(k, p[keep], q[keep], R[keep], L).cpu().numpy()
+        ref = (radial.radial_auto(cls, xi[keep], R[keep], L, G, G) * radial.n_prime(p[keep], q[keep])[:, None]).to_float()
+        err = envelope_err(A.T, ref, xi[keep])
+        print(f"  radial L={L} worst scaled err {err.max():.2e}", flush=True)
+        assert err.max() < 1e-13
+
+
+@pytest.mark.parametrize("cls", [2, 3, 6])
+def test_radial_far_side_of_narrow_kernels(lib, cls):
+    """Kernels much narrower than the pair Gaussian (g >> xi) at large T: the
+    F(-R) side of the large-T route is damped only by exp(-xi T / (xi + g)),
+    so it must be kept far beyond the T where it vanishes for g = 0.  Single
+    terms, each scored on its own envelope, against the oracle."""
+    from oracle import radial
+    from oracle.factor import TermFactor
+    rng = np.random.default_rng(77)
+    pts = []
+    for T in (30.0, 60.0, 107.0, 200.0, 400.0, 600.0):  # exp(-T) stays above the underflow
+        for _ in range(3):
+            xi = 10 ** rng.uniform(-2, -0.5)
+            p = xi * (1 + 10 ** rng.uniform(-0.5, 0.5))
+            q = p * xi / (p - xi)
+            pts.append((p, q, math.sqrt(T / xi)))
+    p = np.array([x[0] for x in pts]); q = np.array([x[1] for x in pts]); R = np.array([x[2] for x in pts])
+    xi = p * q / (p + q)
+    for term in ((1.0, 0.0, 0.0, 5.0), (0.7, 0.0, 0.0, 50.0), (0.4, 1.0, 0.3, 2.0), (0.2, 0.5, 0.0, 8.0)):
+        k = lib.Kernel.from_terms(cls, [term])
+        G = TermFactor((term,))
+        for L in (0, 4, 12):
+            keep = np.array([radial.cancellation_digits(t, L) < 13 for t in xi * R * R])
+            A = lib.aux_radial(k, p[keep], q[keep], R[keep], L).cpu().numpy()
+            ref = (radial.radial_auto(cls, xi[keep], R[keep], L, G, G)
+                   * radial.n_prime(p[keep], q[keep])[:, None]).to_float()
+            err = envelope_err(A.T, ref, xi[keep])
+            # these values are exp(-w R^2) with w R^2 ~ T: a one-ulp change of
+            # xi (which binary64 forms from p and q) moves them by ~T eps
+            tol = 1e-13 + 4e-16 * (xi[keep] * R[keep] ** 2)
+            print(f"far side cls={cls} term={term} L={L}: worst scaled err {err.max():.2e}, "
+                  f"worst err/tol {(err.max(axis=1) / tol).max():.2f}", flush=True)
+            assert np.all(err.max(axis=1) < tol), (term, L)
+
+
 def _negpow_cases():
     sys.path.insert(0, __import__("os").path.join(__import__("os").path.dirname(__file__), "golden"))
     from make_golden import NEGPOW_CASES
