@@ -44,18 +44,18 @@ METRIC = "contracted shell-quartets/s per F12 class at ≤1e-12 rel err; % FP64 
 # SHA-1 covers those files, and traffic is reported as null once they differ.
 # Summary and commands: profiles/contraction_hbm_traffic.md.
 KERNEL_SOURCES = ["f12_big.h", "f12_common.h", "f12_launch.h", "f12_internal.h", "f12_kernels.hip",
-                  "f12_dd.h"] + ["f12_big_lab%d.hip" % i for i in range(7)]
+                  "f12_dd.h", "f12_big_unit.hip"]
 TRAFFIC_RECORD = {
-    "sources_sha1": "a6c995696cfa5fca2d19a3ddde8d9896b03b78eb",
+    "sources_sha1": "176023899205a1c8c032d67df419661d2421f6c2",
     "fetch_scale": 1048576 / 524299.5,
     "write_scale": 1.0,
-    "contraction_bytes_per_launch": 7.12356e7 + 8.73574e7,
-    "aux_bytes_per_launch": 7.90192e8 + 1.41157e9,
+    "contraction_bytes_per_launch": 6.44345e7 + 7.92805e7,
+    "aux_bytes_per_launch": 7.38886e8 + 1.39116e9,
     # FP64 flops issued per launch, 64 lanes x (2 SQ_INSTS_VALU_FMA_F64 + SQ_INSTS_VALU_MUL_F64 +
     # SQ_INSTS_VALU_ADD_F64), from one more --pmc pass (profiles/contraction_fp64_counters.md);
     # an upper bound, since lanes masked off are counted too
-    "contraction_hw_fp64_flops_per_launch": 3.420e10,
-    "aux_hw_fp64_flops_per_launch": 1.128e10,
+    "contraction_hw_fp64_flops_per_launch": 3.117e10,
+    "aux_hw_fp64_flops_per_launch": 1.095e10,
 }
 
 

@@ -1,7 +1,8 @@
 """Build libf12int.so (HIP, gfx950) in-tree with hipcc.
 
-Each source is compiled to an object in parallel (the shape-specialised
-contraction kernels are spread over several files), then linked."""
+Each source is compiled to an object in parallel, the shape-specialised
+contraction kernels (f12_big_unit.hip) once per (l_a + l_b, ket precision),
+then linked."""
 import os
 import subprocess
 import sys
@@ -10,8 +11,10 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libf12int.so")
-SOURCES = ["f12_host.cpp", "f12_batch.cpp", "f12_kernels.hip", "f12_k2.hip"] + ["f12_big_lab%d.hip" % k for k in range(7)] + \
-    ["f12_big_ff%d.hip" % k for k in range(7)]
+# (source, object name, extra defines)
+SOURCES = [(s, os.path.splitext(s)[0], []) for s in ("f12_host.cpp", "f12_batch.cpp", "f12_kernels.hip", "f12_k2.hip")]
+SOURCES += [("f12_big_unit.hip", "f12_big_unit_%d_%d" % (lab, prec), ["-DF12_LAB=%d" % lab, "-DF12_PREC=%d" % prec])
+            for prec in (0, 1) for lab in range(7)]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
 
@@ -28,13 +31,14 @@ def build(verbose=False, jobs=None):
     headers.append(os.path.join(os.path.dirname(HERE), "include", "f12int.h"))
     newest_h = max(os.path.getmtime(h) for h in headers)
 
-    def compile_one(src):
-        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+    def compile_one(job):
+        src, name, defs = job
+        obj = os.path.join(objdir, name + ".o")
         if incremental and os.path.exists(obj):
             t = os.path.getmtime(obj)
             if t > os.path.getmtime(os.path.join(CSRC, src)) and t > newest_h:
                 return src, obj, subprocess.CompletedProcess([], 0, "", "")
-        cmd = [hipcc] + FLAGS + ["-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc] + FLAGS + defs + ["-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         return src, obj, r
 

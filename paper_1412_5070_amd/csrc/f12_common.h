@@ -1,5 +1,5 @@
 // Device helpers shared by the contraction kernels (f12_kernels.hip and the
-// per-shape kernels f12_big_lab*.hip): Hermite index maps, Cartesian
+// per-shape kernels of f12_big.h): Hermite index maps, Cartesian
 // component order, E coefficients and the launch argument block.
 #pragma once
 #include <hip/hip_runtime.h>

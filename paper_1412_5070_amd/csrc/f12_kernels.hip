@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__rest
 
 // ---------------------------------------------------------------------------
 // K5/K6: the Hermite integrals and the E.R.E contraction run in the
-// shape-specialised kernels of f12_big.h (instantiated in f12_big_lab*.hip).
+// shape-specialised kernels of f12_big.h (instantiated by f12_big_unit.hip).
 // ---------------------------------------------------------------------------
 
 // ---------------------------------------------------------------------------
@@ -664,44 +664,32 @@ int launch_aux(const KernelDev *K, const PairsDev &bra, const PairsDev &ket, con
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_big_lab0(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_lab1(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_lab2(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_lab3(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_lab4(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_lab5(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_lab6(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_ff0(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_ff1(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_ff2(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_ff3(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_ff4(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_ff5(int, int, const ContractArgs &, unsigned, hipStream_t);
-int launch_big_ff6(int, int, const ContractArgs &, unsigned, hipStream_t);
+// One launcher per (l_a + l_b, ket precision), each built in a translation
+// unit of its own from f12_big_unit.hip.
+template <int LAB, int PREC>
+int launch_big_unit(int lcd, int i5, const ContractArgs &a, unsigned nblocks, hipStream_t st);
+#define F12_UNIT(L)                                                                             \
+  template <> int launch_big_unit<L, 0>(int, int, const ContractArgs &, unsigned, hipStream_t); \
+  template <> int launch_big_unit<L, 1>(int, int, const ContractArgs &, unsigned, hipStream_t);
+F12_UNIT(0) F12_UNIT(1) F12_UNIT(2) F12_UNIT(3) F12_UNIT(4) F12_UNIT(5) F12_UNIT(6)
+#undef F12_UNIT
 
-static int launch_big(int lab, int lcd, int i5, const ContractArgs &a, unsigned nb, hipStream_t st) {
-  if (a.prec == 1) {
-    switch (lab) {
-      case 0: return launch_big_ff0(lcd, i5, a, nb, st);
-      case 1: return launch_big_ff1(lcd, i5, a, nb, st);
-      case 2: return launch_big_ff2(lcd, i5, a, nb, st);
-      case 3: return launch_big_ff3(lcd, i5, a, nb, st);
-      case 4: return launch_big_ff4(lcd, i5, a, nb, st);
-      case 5: return launch_big_ff5(lcd, i5, a, nb, st);
-      case 6: return launch_big_ff6(lcd, i5, a, nb, st);
-      default: return -1;
-    }
-  }
+template <int PREC>
+static int launch_big_p(int lab, int lcd, int i5, const ContractArgs &a, unsigned nb, hipStream_t st) {
   switch (lab) {
-    case 0: return launch_big_lab0(lcd, i5, a, nb, st);
-    case 1: return launch_big_lab1(lcd, i5, a, nb, st);
-    case 2: return launch_big_lab2(lcd, i5, a, nb, st);
-    case 3: return launch_big_lab3(lcd, i5, a, nb, st);
-    case 4: return launch_big_lab4(lcd, i5, a, nb, st);
-    case 5: return launch_big_lab5(lcd, i5, a, nb, st);
-    case 6: return launch_big_lab6(lcd, i5, a, nb, st);
+    case 0: return launch_big_unit<0, PREC>(lcd, i5, a, nb, st);
+    case 1: return launch_big_unit<1, PREC>(lcd, i5, a, nb, st);
+    case 2: return launch_big_unit<2, PREC>(lcd, i5, a, nb, st);
+    case 3: return launch_big_unit<3, PREC>(lcd, i5, a, nb, st);
+    case 4: return launch_big_unit<4, PREC>(lcd, i5, a, nb, st);
+    case 5: return launch_big_unit<5, PREC>(lcd, i5, a, nb, st);
+    case 6: return launch_big_unit<6, PREC>(lcd, i5, a, nb, st);
     default: return -1;
   }
+}
+
+static int launch_big(int lab, int lcd, int i5, const ContractArgs &a, unsigned nb, hipStream_t st) {
+  return a.prec == 1 ? launch_big_p<1>(lab, lcd, i5, a, nb, st) : launch_big_p<0>(lab, lcd, i5, a, nb, st);
 }
 
 int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb, const int64_t *qk,
