@@ -48,7 +48,8 @@ typedef enum {
   F12_ELMAX = -3,     /* angular momentum above the supported maximum           */
   F12_ENOMEM = -4,    /* host or device allocation failed                       */
   F12_EDEVICE = -5,   /* a HIP runtime call failed                              */
-  F12_EBUFSIZE = -6   /* output buffer too small for the requested range        */
+  F12_EBUFSIZE = -6,  /* output buffer too small for the requested range        */
+  F12_ENONFINITE = -7 /* a kernel produced a non-finite value (f12_stream_status) */
 } f12_status;
 
 typedef enum {
@@ -211,6 +212,16 @@ typedef enum {
                       /* primitives stay in binary64.                                */
 } f12_precision;
 
+/* Several factor sets in one call: f12_eval of the range with each of
+ * kernels[0..nset) (all of the list's class), set s written at
+ * d_out + s * n, n = offsets[q_end] - offsets[q_begin] (layout
+ * [set][quartet block]); out_capacity must hold nset * n doubles (else
+ * F12_EBUFSIZE).  The sets run one after the other on `stream` and share the
+ * list's radial-derivative buffer.  F12_EINVAL for nset < 1, a null kernel
+ * or a class mismatch; otherwise as f12_eval. */
+int f12_eval_sets(f12_quartets *q, const f12_kernel *const *kernels, int32_t nset, int64_t q_begin,
+                  int64_t q_end, double *d_out, int64_t out_capacity, void *stream);
+
 /* f12_eval with the contraction arithmetic chosen by `precision`
  * (F12_FP64 gives exactly f12_eval's result).  F12_EINVAL for an unknown
  * precision; otherwise as f12_eval. */
@@ -304,7 +315,13 @@ int f12_aux_radial(const f12_kernel *k, int64_t n, const double *d_p, const doub
 int f12_aux_w_column(double alpha0, int32_t is_int, int32_t m_lo, int32_t m_hi, double x,
                      double *out);
 
-/* Synchronises `stream` and reports a HIP error if one occurred. */
+/* Synchronises `stream` and reports what the device saw: F12_EDEVICE if a
+ * HIP call or launch failed; F12_ENONFINITE if, since the last call on this
+ * device, a kernel of the library produced a non-finite value (a radial
+ * derivative A_n of Eq. (bfinal) or an output element; for example from
+ * contraction coefficients so large that their products overflow).  The
+ * device keeps one such fault word, shared by every stream and handle on it;
+ * this call reads it and clears it.  F12_OK otherwise. */
 int f12_stream_status(void *stream);
 const char *f12_strerror(int32_t status);
 

@@ -706,7 +706,7 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
     if (e < nu) Uf[e] = uacc[k];
   }
   __syncthreads();
-  hrr_store(Uf, la, lb, lc, ld, nf, CD, a.out + o, tid, NT);
+  hrr_store(Uf, la, lb, lc, ld, nf, CD, a.out + o, tid, NT, a.fault);
   __syncthreads();  // Uf is rewritten by the next quartet
   }
 }

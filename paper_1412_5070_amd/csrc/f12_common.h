@@ -127,7 +127,8 @@ struct ContractArgs {
   int la, lb, lc, ld, i5;
   double *out;
   int64_t out_base;
-  int prec;  // 0: FP64; 1: ket transform in split FP32
+  int prec;    // 0: FP64; 1: ket transform in split FP32
+  int *fault;  // the device's fault word (set on a non-finite output element)
 };
 
 // Position of one-centre component (fx, fy, fz) among |f| = l_c .. l_c+l_d.
@@ -165,9 +166,10 @@ __device__ inline void e_onecentre(double q, double XQC, int Lcd, double *E) {
 }
 
 // (ab|f) -> (ab|cd) by x_D^d = sum_k C(d,k) (C_x - D_x)^(d-k) x_C^k (and y, z),
-// then the store of the contracted block; U[ab * nf + f] in LDS.
+// then the store of the contracted block; U[ab * nf + f] in LDS.  A non-finite
+// element sets the device's fault word.
 __device__ inline void hrr_store(const double *U, int la, int lb, int lc, int ld, int nf,
-                                 const double CD[3], double *out, int tid, int nt) {
+                                 const double CD[3], double *out, int tid, int nt, int *fault) {
   const int nd = ncart(ld), ncd = ncart(lc) * nd;
   const int nab = ncart(la) * ncart(lb);
   for (int e = tid; e < nab * ncd; e += nt) {
@@ -187,6 +189,7 @@ __device__ inline void hrr_store(const double *U, int la, int lb, int lc, int ld
         }
       }
     }
+    if (!isfinite(s)) *fault = 1;
     out[e] = s;
   }
 }

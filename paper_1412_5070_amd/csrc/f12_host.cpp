@@ -34,6 +34,7 @@ extern "C" const char *f12_strerror(int32_t s) {
     case F12_ENOMEM: return "out of memory";
     case F12_EDEVICE: return "HIP runtime error";
     case F12_EBUFSIZE: return "output buffer too small";
+    case F12_ENONFINITE: return "a kernel produced a non-finite value";
     default: return "unknown status";
   }
 }
@@ -41,6 +42,15 @@ extern "C" const char *f12_strerror(int32_t s) {
 extern "C" int f12_stream_status(void *stream) {
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return F12_EDEVICE;
   if (hipGetLastError() != hipSuccess) return F12_EDEVICE;
+  int *fw = fault_word();
+  if (!fw) return F12_EDEVICE;
+  int v = 0;
+  if (hipMemcpy(&v, fw, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return F12_EDEVICE;
+  if (v != 0) {
+    const int zero = 0;
+    if (hipMemcpy(fw, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess) return F12_EDEVICE;
+    return F12_ENONFINITE;
+  }
   return F12_OK;
 }
 
@@ -1374,6 +1384,25 @@ extern "C" int f12_eval(f12_quartets *q, const f12_kernel *k, int64_t q_begin, i
   if (q_begin == q_end) return F12_OK;
   q->stage_qa = q->stage_qe = -1;
   return eval_range(q, k, q_begin, q_end, d_out, q->d_A.ptr, q->a_cap_prims, (hipStream_t)stream);
+}
+
+extern "C" int f12_eval_sets(f12_quartets *q, const f12_kernel *const *kernels, int32_t nset,
+                             int64_t q_begin, int64_t q_end, double *d_out, int64_t out_capacity,
+                             void *stream) {
+  if (!q || !kernels || nset < 1 || !d_out || q_begin < 0 || q_end > q->nq || q_begin > q_end)
+    return F12_EINVAL;
+  for (int32_t s = 0; s < nset; ++s)
+    if (!kernels[s] || kernels[s]->cls != q->cls) return F12_EINVAL;
+  const int64_t n = q->qoff[q_end] - q->qoff[q_begin];
+  if (n > 0 && (int64_t)nset > out_capacity / n) return F12_EBUFSIZE;
+  if (q_begin == q_end) return F12_OK;
+  q->stage_qa = q->stage_qe = -1;
+  for (int32_t s = 0; s < nset; ++s) {
+    int st = eval_range(q, kernels[s], q_begin, q_end, d_out + (int64_t)s * n, q->d_A.ptr, q->a_cap_prims,
+                        (hipStream_t)stream);
+    if (st) return st;
+  }
+  return F12_OK;
 }
 
 extern "C" int f12_eval_precision(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,

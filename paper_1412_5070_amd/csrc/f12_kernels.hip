@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <math.h>
+#include <mutex>
 
 #include "f12_internal.h"
 #include "f12_common.h"
@@ -14,6 +15,29 @@ namespace f12 {
 
 #define F12_PI52 17.493418327624862846  // pi^(5/2)
 #define F12_SQRTPI 1.7724538509055160273
+
+// Fault word of the device: a kernel that produces a non-finite value (an
+// A_n, an output element) sets it to 1 with a plain store from the lane that
+// found it; f12_stream_status reads and clears it.
+__device__ int fault_word_dev;
+
+namespace {
+constexpr int kMaxDev = 64;
+std::mutex g_fault_mu;
+int *g_fault_ptr[kMaxDev] = {};
+}  // namespace
+
+int *fault_word() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
+  std::lock_guard<std::mutex> lock(g_fault_mu);
+  if (!g_fault_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(fault_word_dev)) != hipSuccess || !ptr) return nullptr;
+    g_fault_ptr[dev] = (int *)ptr;
+  }
+  return g_fault_ptr[dev];
+}
 
 
 // ---------------------------------------------------------------------------
@@ -559,7 +583,7 @@ __global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__rest
                                                   const int64_t *__restrict__ qk,
                                                   const int64_t *__restrict__ qprim, int64_t qa,
                                                   int64_t nqc, int64_t p0, int64_t np, int L,
-                                                  double *__restrict__ A) {
+                                                  double *__restrict__ A, int *fault) {
   __shared__ double s_xi[F12_NT_AUX], s_u[F12_NT_AUX], s_np[F12_NT_AUX];
   __shared__ int s_perm[F12_NT_AUX];
   __shared__ int s_cnt[AUX_BINS], s_off[AUX_BINS];
@@ -624,7 +648,13 @@ __global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__rest
   } else {
     aux_large<H>(K, xi, sqrt(u), L, minus_budget(T, L), a);
   }
-  for (int n = 0; n <= L; ++n) A[n * np + base + me] = a[n] * Np;
+  bool bad = false;
+  for (int n = 0; n <= L; ++n) {
+    const double v = a[n] * Np;
+    bad |= !isfinite(v);
+    A[n * np + base + me] = v;
+  }
+  if (bad) *fault = 1;
 }
 
 
@@ -654,13 +684,15 @@ int launch_aux(const KernelDev *K, const PairsDev &bra, const PairsDev &ket, con
                const int64_t *qk, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
                int64_t np, int L, double *A, hipStream_t stream, int heavy) {
   if (np <= 0) return 0;
+  int *fw = fault_word();
+  if (!fw) return -1;
   const int64_t nbk = (np + F12_NT_AUX - 1) / F12_NT_AUX;
   if (heavy)
     hipLaunchKernelGGL(aux_kernel<true>, dim3((unsigned)nbk), dim3(F12_NT_AUX), 0, stream, K, bra, ket, qb,
-                       qk, qprim, qa, nqc, p0, np, L, A);
+                       qk, qprim, qa, nqc, p0, np, L, A, fw);
   else
     hipLaunchKernelGGL(aux_kernel<false>, dim3((unsigned)nbk), dim3(F12_NT_AUX), 0, stream, K, bra, ket, qb,
-                       qk, qprim, qa, nqc, p0, np, L, A);
+                       qk, qprim, qa, nqc, p0, np, L, A, fw);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -698,6 +730,8 @@ int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
                     double *out, int64_t out_base, hipStream_t stream, int64_t grid, int prec) {
   if (nqc <= 0) return 0;
   ContractArgs a;
+  a.fault = fault_word();
+  if (!a.fault) return -1;
   a.bra = bra;
   a.ket = ket;
   a.qb = qb;

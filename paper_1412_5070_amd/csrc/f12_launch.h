@@ -22,6 +22,11 @@ int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
                     double *out, int64_t out_base, hipStream_t stream, int64_t grid = 0,
                     int prec = 0);
 
+// Device address of the current device's fault word (looked up once per
+// device; nullptr if the lookup fails).  Kernels set the word to 1 when they
+// produce a non-finite value.
+int *fault_word();
+
 // Radial derivatives A_n (n = 0..L) for explicit (p, q, R) triples (diagnostic path).
 int launch_aux_points(const KernelDev *K, int64_t n, const double *p, const double *q,
                       const double *R, int L, int route, double *A, hipStream_t stream);

@@ -57,6 +57,7 @@ EXPORTS = {
     "f12_quartets_destroy": (None, [_vp]),
     "f12_eval": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp]),
     "f12_eval_precision": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i32, _vp]),
+    "f12_eval_sets": (_c_i32, [_vp, _P(_vp), _c_i32, _c_i64, _c_i64, _vp, _c_i64, _vp]),
     "f12_eval_noalloc": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp]),
     "f12_eval_stage": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i32, _vp]),
     "f12_quartets_scratch_prims": (_c_i32, [_vp, _P(_c_i64)]),
@@ -299,7 +300,20 @@ def eval_into(quartets, kernel, out, q_begin=0, q_end=None, stream=None):
     return out
 
 
+def eval_sets(quartets, kernels, out, q_begin=0, q_end=None, stream=None):
+    """Enqueue f12_eval_sets: one kernel per factor set, output [set][quartet block]."""
+    import torch
+    if q_end is None:
+        q_end = quartets.n_quartets
+    assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+    arr = (_vp * len(kernels))(*[k.handle for k in kernels])
+    _check(_lib.f12_eval_sets(quartets.handle, arr, len(kernels), int(q_begin), int(q_end), _vp(out.data_ptr()),
+                              out.numel(), _stream_ptr(stream)), "f12_eval_sets")
+    return out
+
+
 FP64, SPLIT_FP32 = 0, 1
+ENONFINITE = -7
 
 
 def eval_precision(quartets, kernel, out, precision, q_begin=0, q_end=None, stream=None):

@@ -39,6 +39,18 @@ def test_strerror():
     from paper_1412_5070_amd import f12int
     assert f12int._lib.f12_strerror(0) == b"ok"
     assert b"factor" in f12int._lib.f12_strerror(-2)
+    assert b"non-finite" in f12int._lib.f12_strerror(-7)
+
+
+def test_eval_sets_validation_before_device():
+    """f12_eval_sets rejects null handles, nset < 1 and a null kernel array
+    before any device work."""
+    from paper_1412_5070_amd import f12int
+    lib = f12int._lib
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.f12_eval_sets(None, arr, 1, 0, 0, None, 0, None) == -1
+    assert lib.f12_eval_sets(None, None, 1, 0, 0, None, 0, None) == -1
+    assert lib.f12_eval_sets(None, arr, 0, 0, 0, None, 0, None) == -1
 
 
 def test_basis_validation():
