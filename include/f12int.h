@@ -43,7 +43,8 @@ typedef enum {
   F12_EPARAM = -2,    /* factor parameters rejected (mu <= 0, non-finite, n   */
                       /* violating n > -rho/2 - 1 for rho < -2, or a kernel     */
                       /* term the library does not support: a negative integer  */
-                      /* power, a power <= -2, b < 0, or too many terms/chains  */
+                      /* power, a power <= -2, b < 0 with a non-integer power,  */
+                      /* or too many terms/chains                              */
                       /* or too wide a range of powers in one chain)           */
   F12_ELMAX = -3,     /* angular momentum above the supported maximum           */
   F12_ENOMEM = -4,    /* host or device allocation failed                       */
@@ -120,11 +121,13 @@ int f12_kernel_create(int32_t cls, const f12_factor *f, const f12_factor *fp, f1
  * nfp = 0 and fp_terms = NULL meaning f' = f; f' is used by I4 and I6).  Any
  * such factor goes through the same term tables and kernels as Eq. (rs12):
  * Gaussian geminals sum_i c_i exp(-g_i r^2) (the Gaussian fits of Ten-no's
- * exponential), their products with powers of r, growing or bounded
- * exponentials.  The kernels k_i are formed from f as for Eq. (rs12):
- * I2 f/r, I3 and I5 f, I4 f f', I6 f_r f'_r.  Each term needs g >= 0,
- * b >= 0 and either an integer alpha >= 0 or a non-integer alpha > -1
- * (else F12_EPARAM; a decaying exponential, b < 0, is not supported);
+ * exponential), their products with powers of r, growing exponentials,
+ * and decaying ones: Ten-no's exponential exp(-gamma r) is the single term
+ * (1, 0, -gamma, 0).  The kernels k_i are formed from f as for Eq. (rs12):
+ * I2 f/r, I3 and I5 f, I4 f f', I6 f_r f'_r.  Each term needs g >= 0 and
+ * either an integer alpha >= 0 or a non-integer alpha > -1, and a term with
+ * b < 0 an integer alpha (else F12_EPARAM; a kernel whose decaying terms
+ * share a power family with non-integer powers is rejected the same way);
  * 1 <= nf <= 96 (else F12_EINVAL). */
 int f12_kernel_create_terms(int32_t cls, int32_t nf, const double *f_terms, int32_t nfp,
                             const double *fp_terms, f12_kernel **out);

@@ -151,6 +151,21 @@ def gaussian_rates(cls, fac, facp):
     return [0.0]
 
 
+def term_peaks(cls, fac, facp):
+    """(b, g) of the kernel's exponential factors e^{b r - g r^2} for factors
+    given by their terms (used to place quadrature panels around the peak of
+    each term's product with the pair Gaussian); [] for Eq. (rs12) factors."""
+    def bg(f):
+        return sorted({(float(b), float(g)) for (c, a, b, g) in f.terms})
+    if not isinstance(fac, TermFactor) and not isinstance(facp, TermFactor):
+        return []
+    if cls in (2, 3, 5):
+        return bg(fac) if isinstance(fac, TermFactor) else []
+    if cls in (4, 6) and isinstance(fac, TermFactor) and isinstance(facp, TermFactor):
+        return sorted({(b1 + b2, g1 + g2) for (b1, g1) in bg(fac) for (b2, g2) in bg(facp)})
+    return []
+
+
 def growth_rate(cls, fac, facp):
     """Largest exponential growth rate b of K_i (used to place quadrature panels)."""
     if isinstance(fac, TermFactor) or isinstance(facp, TermFactor):

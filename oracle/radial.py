@@ -30,12 +30,12 @@ import math
 import numpy as np
 from . import dd
 from .quadrature import gauss_legendre, tanh_sinh
-from .factor import TermFactor, gaussian_rates, growth_rate, kernel_times_r
+from .factor import TermFactor, gaussian_rates, growth_rate, kernel_times_r, term_peaks
 
 N_PEAK = 8  # Gauss-Legendre panels across each peak of the integrand
 
 
-def _interior_edges(xi, R, lo, hi, c, w, b, mus):
+def _interior_edges(xi, R, lo, hi, c, w, b, mus, peaks=()):
     """Panel edges inside [lo, hi] (arrays over quartets, shape (P, M)).
 
     The integrand has up to two kinds of peaks: the pair Gaussian shifted by
@@ -46,9 +46,13 @@ def _interior_edges(xi, R, lo, hi, c, w, b, mus):
     side).  Each peak gets N_PEAK panels of its own: a kernel much narrower
     than the pair Gaussian (mu >> xi) puts all its weight in a region far
     smaller than R, which a subdivision of [lo, hi] into equal panels would
-    resolve poorly.  Edges are clipped to [lo, hi] and sorted; the gaps
-    between peaks are single panels (the integrand there is below exp(-144)
-    of its peaks)."""
+    resolve poorly.  For a factor given by its terms, each term's
+    exp(bt r - gt r^2) times the pair Gaussian peaks at
+    (2 xi R + bt) / (2 (xi + gt)) with width (xi + gt)^-1/2 and gets panels
+    as well (this places decaying terms, bt < 0, whose peak lies below R or
+    at r = 0).  Edges are clipped to [lo, hi] and sorted; the gaps between
+    peaks are single panels (the integrand there is below exp(-144) of its
+    peaks)."""
     cand = [lo + 0.0 * xi, hi + 0.0 * xi]
     for k in range(N_PEAK + 1):
         cand.append(c - 14.0 * w + 28.0 * w * k / N_PEAK)
@@ -60,6 +64,11 @@ def _interior_edges(xi, R, lo, hi, c, w, b, mus):
             e = rstar + b / (2.0 * (mu + xi)) + 12.0 * sig
             for k in range(N_PEAK + 1):
                 cand.append(a + (e - a) * k / N_PEAK)
+    for (bt, gt) in peaks:
+        sig = 1.0 / np.sqrt(xi + gt)
+        ctr = (2.0 * xi * R + bt) / (2.0 * (xi + gt))
+        for k in range(N_PEAK + 1):
+            cand.append(ctr - 14.0 * sig + 28.0 * sig * k / N_PEAK)
     E = np.stack(cand, axis=1)
     E = np.clip(E, lo[:, None], hi[:, None])
     E.sort(axis=1)
@@ -81,6 +90,9 @@ def _nodes(xi, R, cls, fac, facp):
         if mu > 0:
             rstar = xi * R / (mu + xi)
             lo = np.minimum(lo, rstar - 12.0 / np.sqrt(mu + xi))
+    peaks = term_peaks(cls, fac, facp)
+    for (bt, gt) in peaks:
+        lo = np.minimum(lo, (2.0 * xi * R + bt) / (2.0 * (xi + gt)) - 14.0 / np.sqrt(xi + gt))
     lo = np.maximum(lo, a1)
     xg, wg = gauss_legendre(48)
     xt, wt, ct = tanh_sinh()
@@ -101,7 +113,7 @@ def _nodes(xi, R, cls, fac, facp):
     rr, ww = gl_panel(a1, lo)
     parts_r.append(rr)
     parts_w.append(ww)
-    E = _interior_edges(xi, R, lo, hi, c, w, b, mus)
+    E = _interior_edges(xi, R, lo, hi, c, w, b, mus, peaks)
     for k in range(E.shape[1] - 1):
         rr, ww = gl_panel(E[:, k], E[:, k + 1])
         parts_r.append(rr)
@@ -335,6 +347,9 @@ def radial_derivatives_mp(cls, xi, R, nmax, fac, facp, extra_digits=None):
             if mu > 0:
                 rstar = xi_m * R_m / (mu + xi_m)
                 lo = min(lo, rstar - 12 / mp.sqrt(mu + xi_m))
+        peaks = term_peaks(cls, fac, facp)
+        for (bt, gt) in peaks:
+            lo = min(lo, (2 * xi_m * R_m + bt) / (2 * (xi_m + gt)) - 14 / mp.sqrt(xi_m + gt))
         lo = max(lo, a1)
         gl = mp.calculus.quadrature.GaussLegendre(mp.mp)
         ts = mp.calculus.quadrature.TanhSinh(mp.mp)
@@ -354,7 +369,7 @@ def radial_derivatives_mp(cls, xi, R, nmax, fac, facp, extra_digits=None):
         # interior edges from the binary64 placement; the ends stay exact
         Ef = _interior_edges(np.array([float(xi_m)]), np.array([float(R_m)]), np.array([float(lo)]),
                              np.array([float(hi)]), np.array([float(c)]), np.array([float(w)]), float(b),
-                             mus)[0]
+                             mus, peaks)[0]
         edges = [lo] + [mp.mpf(float(v)) for v in Ef[1:-1]] + [hi]
         edges = [min(max(v, lo), hi) for v in edges]
         pts += [(edges[k], edges[k + 1], gnodes) for k in range(len(edges) - 1)]

@@ -702,9 +702,10 @@ extern "C" int f12_kernel_create_terms(int32_t cls, int32_t nf, const double *f_
     for (int i = 0; i < n; ++i) {
       const double c = t[4 * i], a = t[4 * i + 1], b = t[4 * i + 2], g = t[4 * i + 3];
       if (!std::isfinite(c) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(g)) return F12_EPARAM;
-      if (g < 0.0 || b < 0.0) return F12_EPARAM;
+      if (g < 0.0) return F12_EPARAM;
       const bool integer = a == std::floor(a);
       if ((integer && a < 0.0) || (!integer && a <= -1.0)) return F12_EPARAM;
+      if (b < 0.0 && !integer) return F12_EPARAM;  // decaying terms: integer powers only
       add_term(e, {c, a, b, g});
     }
     return F12_OK;
@@ -775,7 +776,9 @@ int kernel_from_factors(int32_t cls, const Expr &ef, const Expr &efp, f12_kernel
       chains.push_back({t.b, t.g, fi, {}});
       ci = (int)chains.size() - 1;
     }
-    if (t.b < 0.0) return F12_EPARAM;  // the ladders assume b >= 0
+    // decaying chains (b < 0) run the downward ladders, written for integer
+    // families with non-negative powers
+    if (t.b < 0.0 && !(fams[fi].is_int && m >= 0)) return F12_EPARAM;
     chains[ci].tm.push_back({m, dd{t.c, t.clo}});
   }
   if ((int)chains.size() > MAX_CHAINS || (int)e.size() > MAX_TERMS ||
@@ -824,6 +827,9 @@ int kernel_from_factors(int32_t cls, const Expr &ef, const Expr &efp, f12_kernel
     if (D.chains[c].m_max - D.chains[c].m_min + LTOT_MAX + 1 > NW_LIGHT) D.heavy = 1;
   }
   if (D.negint) D.heavy = 1;
+  D.negb = 0;
+  for (int c = 0; c < D.nchains; ++c)
+    if (D.chains[c].b < 0.0) D.heavy = D.negb = 1;  // the downward ladders live in the heavy kernels
   // ---- W tables
   const int nx = (int)std::lround((WX_HI - WX_LO) * WX_INVH) + 1;
   for (size_t fi = 0; fi < fams.size(); ++fi) {

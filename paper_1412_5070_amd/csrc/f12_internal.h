@@ -51,6 +51,7 @@ struct KernelDev {
   int32_t negint;  // 1 if an integer family has negative powers (finite parts with log terms)
   int32_t heavy;   // negint, or a chain spanning more than NW_LIGHT orders in the large-T route
   int32_t singular;  // a term r^a with a <= -1 (finite parts; their singular pieces cancel across chains)
+  int32_t negb;      // a decaying chain (b < 0)
   ChainDesc chains[MAX_CHAINS];
   TermDesc terms[MAX_TERMS];
   FamilyDesc fam[MAX_FAMILIES];

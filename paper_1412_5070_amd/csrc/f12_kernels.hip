@@ -15,6 +15,7 @@ namespace f12 {
 
 #define F12_PI52 17.493418327624862846  // pi^(5/2)
 #define F12_SQRTPI 1.7724538509055160273
+#define F12_PI 3.14159265358979323846
 
 // Fault word of the device: a kernel that produces a non-finite value (an
 // A_n, an output element) sets it to 1 with a plain store from the lane that
@@ -108,6 +109,38 @@ __device__ double w_asym(double a, double X) {
 // binary64).  D^n(phi/R) is then formed from the R-jet of phi.
 // ---------------------------------------------------------------------------
 
+// W~_m(X) = e^{X^2} W_m(X), m = mlo..mhi (integer m >= 0), for X < WX_LO, the
+// region below the tables that decaying chains (b < 0) reach: their F(+-R)
+// is e^{-T} W~ there, since E(x) e^{-gam y^2} = e^{-xi x^2} exactly.  W_m is
+// the minimal solution of W_{m+1} = X W_m + (m/2) W_{m-1} for X < 0 (the
+// other solution integrates over (-inf, 0] and is larger by ~e^{X^2}); the
+// recurrence runs downward from mhi + 40, where the ratio of the two
+// solutions changes by ~2 X^2 / m > 4 per order, and W~_0 =
+// sqrt(pi)/2 erfcx(-X) fixes the scale.  Om[m - mlo] = gp isq^(m - mlo) W~_m.
+__device__ inline void w_far_scaled(double X, int mlo, int mhi, double gp, double isq, double *Om) {
+  double wa = 0.0, wb = 1.0;  // W~_{m+1}, W~_m at m = top (up to a common scale)
+  for (int m = mhi + 40; m >= 1; --m) {
+    if (m <= mhi && m >= mlo) Om[m - mlo] = wb;
+    const double wn = (2.0 / m) * (wa - X * wb);  // W~_{m-1}
+    wa = wb;
+    wb = wn;
+    const double sc = fabs(wb) > 1e200 ? 1e-200 : (fabs(wb) < 1e-200 ? 1e200 : 1.0);
+    if (sc != 1.0) {
+      wa *= sc;
+      wb *= sc;
+      for (int k = m - 1 < mlo ? mlo : m - 1; k <= mhi; ++k)
+        if (k >= m) Om[k - mlo] *= sc;
+    }
+  }
+  if (mlo == 0) Om[0] = wb;
+  const double lam = 0.5 * F12_SQRTPI * erfcx(-X) / wb;
+  double g = gp * lam;
+  for (int m = mlo; m <= mhi; ++m) {
+    Om[m - mlo] *= g;
+    g *= isq;
+  }
+}
+
 // H ("heavy"): the kernel has negative integer powers (finite parts with log
 // terms) or chains whose orders span more than NW_LIGHT; a uniform property
 // of the kernel, so each launch takes one instantiation, and the common
@@ -145,14 +178,19 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
     // h_m(y) = [r^m] e^{-gam (r - y)^2} = gam^{m/2} e^{-X^2} Hphys_m(X) / m!
     const bool negint = H && F.is_int && ch.m_min < 0;
     const double hlg = negint ? 0.5 * log(gam) : 0.0;
-    const bool do_minus = K->singular ? any_minus : kap * T < mbudget;
+    // a decaying chain's sides compare as exp(-X_+^2), X_+ = sqrt(gam) (kappa R + c_s),
+    // and are alike once X_+ < 0 (the pair Gaussian's centre inside the decay length)
+    const double Xp = sqg * (kap * R + cs);
+    const bool do_minus = K->singular ? any_minus
+                          : (H && b < 0.0 ? (Xp < 0.0 || Xp * Xp < mbudget) : kap * T < mbudget);
     for (int sgn = 1; sgn >= -1; sgn -= 2) {
       if (sgn < 0 && !do_minus) break;
       const double x = sgn * R;
       const double y = kap * x + cs;
       const double X = sqg * y;
-      if (sgn < 0 && X < WX_LO) break;  // below exp(-110) of this chain's F(R)
-      const double E = exp(e0 + a1 * x - a2 * x * x);
+      const bool far = H && b < 0.0 && X < WX_LO;  // decaying chain below the tables
+      if (sgn < 0 && X < WX_LO && !far) break;     // below exp(-110) of this chain's F(R)
+      const double E = far ? exp(-xi * x * x) : exp(e0 + a1 * x - a2 * x * x);
       double Om[H ? NW_MAX : NW_LIGHT];
       {
         // gam^{-(alpha0+m+1)/2} = g0 * isq^m
@@ -162,7 +200,9 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
         } else {
           for (int i = 0; i < -mlo; ++i) gp *= sqg;
         }
-        if (X >= WX_HI) {
+        if (far) {
+          w_far_scaled(X, mlo, mhi, gp, isq, Om);
+        } else if (X >= WX_HI) {
           for (int m = mlo; m <= mhi; ++m) {
             Om[m - mlo] = gp * w_asym(F.alpha0 + m, X);
             gp *= isq;
@@ -235,7 +275,7 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
           // Omega_mt^(mt+1+j)(y) = mt! d^j/dy^j exp(-gam y^2) = mt! e^{-gam y^2} Q_j(y)
           double fact = 1.0;
           for (int i = 2; i <= mt; ++i) fact *= i;
-          const double eg = ct * fact * exp(-gam * y * y);
+          const double eg = ct * fact * (far ? 1.0 : exp(-gam * y * y));  // far: scaled by e^{X^2}
           double q0 = 1.0, q1 = -2.0 * gam * y;
           for (int k = mt + 1; k <= L; ++k) {
             const int j = k - mt - 1;
@@ -321,11 +361,72 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
 // 64 (the others, T < 6)
 constexpr int JMAX_HEAVY = 112, JMAX_LIGHT = 64;
 
+// Decaying chains (b < 0, integer alpha family with m_min >= 0).  With b < 0,
+// S(a, b, gam) is the minimal solution of 2 gam S(a+2) = (a+1) S(a) + b S(a+1):
+// the other solution, the integral over (-inf, 0], is (-1)^a S(a, -b, gam),
+// larger by ~exp(2 |b| r*) at the integrand's peak r*.  Upward the ladder
+// then loses a factor of up to exp(y^2/2) (y = b/sqrt(gam)), and the Phi
+// series of its start values, whose sum is only ~|y|^-(a+1) for y < 0, keeps
+// a truncation tail ~|y|^KPHI / Gamma(KPHI/2) relative to terms of order
+// one.  Up to |y| = Y_UPWARD both stay far below 1e-20 and the upward ladder
+// of the other chains is used.  Beyond it the ladder runs downward (Miller): first
+// from an order far above the top with arbitrary start values down to order
+// 0, where S(0) = 1/2 sqrt(pi/gam) erfcx(|y|/2) fixes the scale (the Miller
+// ratios converge like exp(-|y| / sqrt(2a)) per order at order a), then
+// from the top with the normalised values, adding each S to the M_j it
+// belongs to.  The normalisation is one factor for the whole chain, so its
+// binary64 accuracy is not amplified by the cancellation of the u-series.
+constexpr double Y_UPWARD = 3.0;
+
+__device__ inline void small_ladder_down(const KernelDev *__restrict__ K, const ChainDesc &ch, double b,
+                                         dd gam, dd y, double as, int kmax, int J, dd *M) {
+  const int ks = (int)as;  // a_s = m_min + 1 >= 1 (integer family)
+  const double ay = -y.hi;
+  int extra = (int)(48.0 * sqrt(2.0 * (ks + kmax + 1)) / ay) + 8;
+  if (extra > 600) extra = 600;
+  // pass 1: orders ks + kmax + extra + 1 .. 0
+  const double big = 0x1p600, small = 0x1p-600;
+  dd sa = dd_make(0.0), sb = dd_make(1.0);  // S(o + 1), S(o) at o = top
+  dd rec0 = dd_make(0.0), rec1 = dd_make(0.0);  // S(ks + kmax), S(ks + kmax + 1)
+  const dd g2 = dd_mul(gam, 2.0);
+  for (int o = ks + kmax + extra; o >= 1; --o) {
+    if (o == ks + kmax + 1) rec1 = sb;
+    if (o == ks + kmax) rec0 = sb;
+    // S(o - 1) = (2 gam S(o + 1) - b S(o)) / o
+    const dd sn = dd_div(dd_sub(dd_mul(g2, sa), dd_mul(sb, b)), (double)o);
+    sa = sb;
+    sb = sn;
+    const double sc = fabs(sb.hi) > big ? small : (fabs(sb.hi) < small && sb.hi != 0.0 ? big : 1.0);
+    if (sc != 1.0) {
+      sa = dd_mul(sa, sc);
+      sb = dd_mul(sb, sc);
+      rec0 = dd_mul(rec0, sc);
+      rec1 = dd_mul(rec1, sc);
+    }
+  }
+  // sb = S(0) up to the common scale
+  const double z = 0.5 * ay;
+  const dd s0 = dd_mul(dd_div(dd_sqrt(dd_div(dd_make(F12_PI), gam)), 2.0), erfcx(z));
+  const dd lam = dd_div(s0, sb);
+  dd Sk = dd_mul(rec0, lam), Snext = dd_mul(rec1, lam);  // S(a_s + k), S(a_s + k + 1) at k = kmax
+  // pass 2: k = kmax .. 0, each S(a_s + k) into the M_j of its terms
+  for (int k = kmax; k >= 0; --k) {
+    for (int t = ch.t_begin; t < ch.t_end; ++t) {
+      const int dk = k - (K->terms[t].m - ch.m_min);
+      if (dk >= 0 && !(dk & 1) && (dk >> 1) <= J)
+        M[dk >> 1] = dd_add(M[dk >> 1], dd_mul(Sk, dd{K->terms[t].c, K->terms[t].clo}));
+    }
+    const dd sp = dd_div(dd_sub(dd_mul(g2, Snext), dd_mul(Sk, b)), as + k);  // S(a_s + k - 1)
+    Snext = Sk;
+    Sk = sp;
+  }
+}
+
 template <bool H>
 __device__ void aux_small(const KernelDev *__restrict__ K, double xi, double u, int L, double T,
-                          double *A) {
+                          double *A, int Jset = 0) {
   constexpr int JM = H ? JMAX_HEAVY : JMAX_LIGHT;
-  int J = L + 24 + (int)(4.0 * T);
+  int J = Jset > 0 ? Jset : L + 24 + (int)(4.0 * T);
   if (J > JM) J = JM;
   dd M[JM + 1];
   for (int j = 0; j <= J; ++j) M[j] = dd{0.0, 0.0};
@@ -376,6 +477,10 @@ __device__ void aux_small(const KernelDev *__restrict__ K, double xi, double u, 
     const dd inv2g = dd_div(dd_make(0.5), gam);
     const int span = ch.m_max - ch.m_min;
     const int kmax = span + 2 * J;
+    if (H && b < 0.0 && -y.hi > Y_UPWARD) {
+      small_ladder_down(K, ch, b, gam, y, as, kmax, J, M);
+      continue;
+    }
     dd Sk = Sm1, Snext = S0;
     for (int k = 0; k <= kmax; ++k) {
       // Sk = S(a_s + k)
@@ -531,10 +636,45 @@ __device__ __forceinline__ double t_switch(int L) {
 // r^{-n}; in the lowering route (binary64) that cancellation is damped by
 // e^{-T} only, so the double-double series (exact to T = 14, with the
 // double-double term coefficients) runs up to T = 14.
+// Kernels with decaying chains (b < 0): while the pair Gaussian's centre lies
+// inside a chain's decay length (X_+ < 0, 2 xi R < |b|), F(R) and F(-R) are
+// both ~e^{-T} and the lowering form's terms b^j Omega^(m-j) exceed their
+// sum by up to (|b| / (2 xi R))^m; the double-double series, which needs few
+// terms for such short-ranged kernels, runs up to T = 14 for them as well.
 constexpr double TSW_NEGINT = 14.0;
 __device__ __forceinline__ double t_switch_k(const KernelDev *K, int L) {
   const double sw = t_switch(L);
-  return (K->negint && sw < TSW_NEGINT) ? TSW_NEGINT : sw;
+  return ((K->negint || K->negb) && sw < TSW_NEGINT) ? TSW_NEGINT : sw;
+}
+
+// Short-ranged kernels past the switch.  When every chain decays faster than
+// the pair Gaussian spreads, the u-series of the small-T route converges at
+// any T: for a chain e^{b r} (g = 0, b < 0) its terms fall like
+// (2j+2) rho^j, rho = (2 xi R / b)^2 = 4 xi T / b^2; for a chain with a
+// Gaussian (g > 0) like (kappa T)^j / j!, kappa = xi / (xi + g).  The sum is
+// then O(1) against e^{-T}, so the double-double jet keeps its accuracy.
+// This is the regime (2 xi R < |b|) where the lowering form of a decaying
+// chain cancels.  Returns the number of series terms, or 0 when a chain is
+// long-ranged (g = 0, b >= 0), rho > 1/2, or more than 70 terms would be
+// needed (M_j stays within the double range up to there).
+__device__ inline int short_range_terms(const KernelDev *__restrict__ K, double xi, double T, int L) {
+  double jm = 0.0;
+  for (int c = 0; c < K->nchains; ++c) {
+    const double g = K->chains[c].g, b = K->chains[c].b;
+    double jc;
+    if (g == 0.0) {
+      if (b >= 0.0) return 0;
+      const double rho = 4.0 * xi * T / (b * b);
+      if (rho > 0.5) return 0;
+      jc = rho > 0.0 ? 46.0 / -log(rho) : 0.0;
+    } else {
+      const double m = T * xi / (xi + g);
+      jc = m + 10.0 * sqrt(m) + 20.0;
+    }
+    jm = fmax(jm, jc);
+  }
+  const int J = L + 10 + (int)ceil(jm);
+  return J <= 70 ? J : 0;
 }
 
 // The F(-R) side of the large-T route.  Against F(R) of its own chain it is
@@ -640,11 +780,14 @@ __global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__rest
   const double xi = s_xi[me], u = s_u[me], Np = s_np[me];
   const double T = xi * u;
   double a[LTOT_MAX + 1];
+  const int Jsr = (H && T >= sw && K->negb) ? short_range_terms(K, xi, T, L) : 0;
   if (T < sw) {
     if (!H && L <= 5 && T < 2.0)
       aux_small_f64<H>(K, xi, u, L, T, a);
     else
       aux_small<H>(K, xi, u, L, T, a);
+  } else if (Jsr > 0) {
+    aux_small<H>(K, xi, u, L, T, a, Jsr);
   } else {
     aux_large<H>(K, xi, sqrt(u), L, minus_budget(T, L), a);
   }
@@ -778,8 +921,11 @@ __global__ void aux_points_kernel(const KernelDev *__restrict__ K, int64_t n,
   if (route == 0) {
     // the production dispatch of aux_kernel
     if (K->heavy) {
+      const int Jsr = K->negb ? short_range_terms(K, xi, T, L) : 0;
       if (T < t_switch_k(K, L))
         aux_small<true>(K, xi, u, L, T, a);
+      else if (Jsr > 0)
+        aux_small<true>(K, xi, u, L, T, a, Jsr);
       else
         aux_large<true>(K, xi, R, L, minus_budget(T, L), a);
     } else {

@@ -34,13 +34,17 @@ FACTOR_SETS = {
 }
 
 
-# A correlation factor given by terms c r^alpha exp(b r - g r^2) instead of the
-# range-separated parameters: three Gaussian geminals (the form of the usual
-# Gaussian fits of an exponential correlation factor), a half-integer power
-# and a growing term, so that every family of the term path is exercised.
+# Correlation factors given by terms c r^alpha exp(b r - g r^2) instead of the
+# range-separated parameters.  G5: three Gaussian geminals (the form of the
+# usual Gaussian fits of an exponential correlation factor), a half-integer
+# power and a growing term, so that every family of the term path is
+# exercised.  STG: Ten-no's exponential exp(-gamma r), gamma = 1.2.  STG3: two
+# decaying exponentials (one times r) and a Gaussian geminal.
 GENERIC_FACTORS = {
     "G5": ((0.3, 0.0, 0.0, 0.2), (0.5, 0.0, 0.0, 1.1), (0.2, 0.0, 0.0, 5.0),
            (0.1, 1.0, 0.4, 0.7), (0.05, 0.5, 0.0, 0.9)),
+    "STG": ((1.0, 0.0, -1.2, 0.0),),
+    "STG3": ((0.8, 0.0, -1.0, 0.0), (0.3, 1.0, -1.5, 0.0), (-0.2, 0.0, 0.0, 0.6)),
 }
 
 

@@ -169,7 +169,7 @@ def factor_key(cls, f, fp, quad):
 
 def _job(args):
     setname, cls, quad = args[:3]
-    if setname == "generic":
+    if setname in ("generic", "stg"):
         from oracle.factor import TermFactor
         from synth import GENERIC_FACTORS, tiny_config
         G = TermFactor(GENERIC_FACTORS[args[3]])
@@ -211,6 +211,8 @@ def build(setname):
         jobs = [(setname, c, q) for c in (5, 2, 3, 4, 6) for q in quads]
     elif setname == "generic":
         jobs = [(setname, c, q, "G5", "G5") for c in (5, 2, 3, 4, 6) for q in FACTOR_QUADS]
+    elif setname == "stg":
+        jobs = [(setname, c, q, f, f) for f in ("STG", "STG3") for c in (5, 2, 3, 4, 6) for q in FACTOR_QUADS]
     elif setname in ("factors", "negpow"):
         base = FACTOR_CASES if setname == "factors" else NEGPOW_CASES
         cases = list(base) + [(3, f, fp) for (c, f, fp) in base if c == 5 and (3, f, fp) not in base]
@@ -222,7 +224,7 @@ def build(setname):
     with Pool(int(os.environ.get("GOLDEN_PROCS", "6"))) as pool:
         for args, val in pool.imap_unordered(_job, jobs):
             sname, cls, quad = args[:3]
-            if sname in ("factors", "negpow", "generic"):
+            if sname in ("factors", "negpow", "generic", "stg"):
                 out[factor_key(cls, args[3], args[4], quad)] = val
             else:
                 out["c%d_%d_%d_%d_%d" % ((cls,) + tuple(quad))] = val

@@ -167,11 +167,11 @@ def test_unsupported_kernel_terms_rejected_before_device():
 
 def test_factor_terms_validation_before_device():
     """f12_kernel_create_terms rejects, before any device work, terms it does
-    not evaluate (a decaying exponential b < 0, a negative Gaussian exponent,
-    a negative integer or a non-integer power <= -1, non-finite values) and
-    malformed lists."""
+    not evaluate (a decaying exponential, b < 0, times a non-integer power, a
+    negative Gaussian exponent, a negative integer or a non-integer power
+    <= -1, non-finite values) and malformed lists."""
     from paper_1412_5070_amd import f12int
-    for bad in ([[1.0, 0.0, -0.5, 0.0]], [[1.0, 0.0, 0.0, -1.0]], [[1.0, -1.0, 0.0, 1.0]],
+    for bad in ([[1.0, 0.5, -0.5, 0.0]], [[1.0, 0.0, 0.0, -1.0]], [[1.0, -1.0, 0.0, 1.0]],
                 [[1.0, -1.5, 0.0, 1.0]], [[np.nan, 0.0, 0.0, 1.0]]):
         with pytest.raises(f12int.F12Error) as e:
             f12int.Kernel.from_terms(3, bad)

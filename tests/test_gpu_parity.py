@@ -444,6 +444,85 @@ def test_radial_far_side_of_narrow_kernels(lib, cls):
             assert np.all(err.max(axis=1) < tol), (term, L)
 
 
+@pytest.mark.parametrize("cls", [2, 3, 4, 6])
+def test_decaying_exponentials_radial_vs_oracle(lib, cls):
+    """Ten-no's exponential exp(-1.2 r) and STG3 (two decaying exponentials
+    and a Gaussian) through f12_kernel_create_terms: radial derivatives at
+    L = 0, 4, 12 (STG) and 0, 8 (STG3) against the oracle, over T from 0 to 3000 and xi from
+    0.01 to 30, so that both ladders of the small-T route (upward for
+    |b|/sqrt(xi) <= 7, downward beyond), the table and the scaled far-side
+    forms of the large-T route, and both signs of X_+ are reached."""
+    from oracle import radial
+    from oracle.factor import TermFactor
+    from synth import GENERIC_FACTORS
+    rng = np.random.default_rng(1225)
+    pts = []
+    for T in (0.0, 1e-4, 0.3, 1.0, 2.5, 4.0, 6.5, 9.0, 15.0, 30.0, 60.0, 150.0, 600.0, 3000.0):
+        for lxi in (-2.0, -1.3, -0.5, 0.5, 1.5):
+            xi = 10 ** (lxi + rng.uniform(-0.1, 0.1))
+            p = xi * (1 + 10 ** rng.uniform(-0.5, 0.5))
+            q = p * xi / (p - xi)
+            pts.append((p, q, math.sqrt(T / xi)))
+    p = np.array([x[0] for x in pts]); q = np.array([x[1] for x in pts]); R = np.array([x[2] for x in pts])
+    xi = p * q / (p + q)
+    for name in ("STG", "STG3"):
+        terms = GENERIC_FACTORS[name]
+        k = lib.Kernel.from_terms(cls, terms, terms)
+        G = TermFactor(terms)
+        for L in ((0, 4, 12) if name == "STG" else (0, 8)):
+            keep = np.array([radial.cancellation_digits(t, L) < 13 for t in xi * R * R])
+            A = lib.aux_radial(k, p[keep], q[keep], R[keep], L).cpu().numpy()
+            ref = (radial.radial_auto(cls, xi[keep], R[keep], L, G, G)
+                   * radial.n_prime(p[keep], q[keep])[:, None]).to_float()
+            sc = (2.0 * xi[keep])[:, None] ** np.arange(L + 1)[None, :]
+            live = np.max(np.abs(ref) / sc, axis=1) > 1e-290  # exp(-T) below the underflow: both zero
+            err = envelope_err(A.T[live], ref[live], xi[keep][live])
+            assert np.all(np.abs(A.T[~live]) < 1e-280)
+            # binary64 forms xi from p and q: values ~exp(-T) move by ~T eps.  From
+            # T = 14 on, where the series does not converge fast enough
+            # (4 xi T / b^2 > ~0.35), the large-T route runs, whose lowering
+            # form cancels by ~10 (|b| / (2 xi R))^L while 2 xi R < |b|: the
+            # documented accuracy limit of decaying kernels with diffuse pairs
+            Tl, xl, Rl = xi[keep][live] * R[keep][live] ** 2, xi[keep][live], R[keep][live]
+            bmax = {2: 1.0, 3: 1.0, 4: 2.0, 6: 2.0}[cls] * max(-t[2] for t in terms)
+            ratio = bmax / np.maximum(2 * xl * Rl, 1e-300)
+            grow = np.where((Tl >= 14.0) & (ratio > 1.0), 10.0 * ratio ** L, 1.0)
+            tol = (1e-13 + 4e-16 * Tl) * grow
+            i = int(np.argmax(err.max(axis=1) / tol))
+            print(f"{name} cls={cls} L={L}: {int(live.sum())} points, worst scaled err {err.max():.2e}, "
+                  f"worst err/tol {(err.max(axis=1) / tol).max():.2f} at T={Tl[i]:.3g} xi={xl[i]:.3g} "
+                  f"(tolerance factor {grow[i]:.3g})", flush=True)
+            assert np.all(err.max(axis=1) < tol), (name, L)
+
+
+@pytest.mark.parametrize("cls", [2, 3, 4, 6, 5])
+def test_decaying_exponentials_vs_golden(lib, cls):
+    """Blocks of the 3-atom s+p molecule with Ten-no's exponential and STG3
+    (f12_kernel_create_terms) against stored oracle values."""
+    import os
+    from synth import GENERIC_FACTORS
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import FACTOR_QUADS, factor_key
+    golden = _golden("stg")
+    shells = _tiny()
+    basis = lib.Basis.from_shells(shells)
+    pairs = lib.Pairs(basis, 1)
+    for name in ("STG", "STG3"):
+        terms = np.array(GENERIC_FACTORS[name])
+        k = lib.Kernel.from_terms(cls, terms, terms)
+        got = run_quads(lib, basis, pairs, k, cls, FACTOR_QUADS)
+        for qd in FACTOR_QUADS:
+            ref = golden[factor_key(cls, name, name, qd)]
+            if cls == 5:
+                ref3 = golden[factor_key(3, name, name, qd)]
+                e = i5_block_err(got[qd], ref, ref3, np.concatenate([shells[qd[0]].exps, shells[qd[1]].exps]),
+                                 i5_vanishes(shells[qd[0]].l, qd[0] == qd[1]))
+            else:
+                e = block_rel_err(got[qd], ref)
+            print(f"{name} cls={cls} {qd} max|I| {np.max(np.abs(ref)):.1e} err {e:.2e}", flush=True)
+            assert e < REL_TOL, (name, qd, e)
+
+
 def _negpow_cases():
     sys.path.insert(0, __import__("os").path.join(__import__("os").path.dirname(__file__), "golden"))
     from make_golden import NEGPOW_CASES

@@ -114,6 +114,16 @@ def _convolution_derivatives(cls, fac, facp, xi, R, nmax=3):
     peak = R + B / xi
     w = 1 / mp.sqrt(xi)
     pts = [0, max(peak - 8 * w, 0) / 2, max(peak - 8 * w, mp.mpf("0.01")), peak, peak + 8 * w, peak + 30 * w]
+    # a factor given by its terms: each term's exp(b r - g r^2) (products of
+    # two for I4/I6) times the pair Gaussian peaks at (2 xi R + b)/(2 (xi + g))
+    if isinstance(fac, TermFactor):
+        bgs = {(b, g) for (_, _, b, g) in fac.terms}
+        if cls in (4, 6):
+            bgs = {(b1 + b2, g1 + g2) for (b1, g1) in bgs for (_, _, b2, g2) in facp.terms}
+        for (b, g) in bgs:
+            ctr = (2 * xi * R + b) / (2 * (xi + g))
+            sg = 1 / mp.sqrt(xi + g)
+            pts += [max(ctr + k * sg, mp.mpf("0.01")) for k in (-8, -2, 0, 2, 8)]
     pts = sorted(set(pts))
     out = []
     for n in range(nmax + 1):
@@ -125,7 +135,7 @@ def _convolution_derivatives(cls, fac, facp, xi, R, nmax=3):
 @pytest.mark.parametrize("cls,fa,fb,T", [(2, "P1", "P1", 5.0), (4, "P1", "P4", 0.3), (4, "P4", "P4", 40.0),
                                          (6, "P1", "P1", 5.0), (4, "P2", "P2", 0.3), (2, "P3", "P3", 5.0),
                                          (6, "P1", "P4", 40.0), (3, "P3", "P3", 40.0), (2, "G5", "G5", 5.0),
-                                         (6, "G5", "G5", 0.3)])
+                                         (6, "G5", "G5", 0.3), (2, "STG", "STG", 5.0), (6, "STG", "STG", 0.3)])
 def test_geminal_kernels_vs_convolution_quadrature(cls, fa, fb, T):
     """(ss|k_i|ss) radial derivatives n = 0..3 of the oracle (Eq. (bfinal) by
     its own panels and derivative forms) against the two-dimensional
@@ -146,6 +156,50 @@ def test_geminal_kernels_vs_convolution_quadrature(cls, fa, fb, T):
     sc = [(2 * xi) ** n for n in range(4)]
     env = max(abs(ref[n]) / sc[n] for n in range(4))
     for n in range(4):
+        err = abs(A[n] - ref[n]) / sc[n] / env
+        assert err < 1e-16, (n, A[n], ref[n], err)
+
+
+@pytest.mark.parametrize("cls,fa,T", [(2, "STG", 0.5), (3, "STG3", 30.0), (4, "STG3", 60.0), (6, "STG", 8.0)])
+def test_decaying_exponentials_small_xi_vs_radial_quadrature(cls, fa, T):
+    """Ten-no's exponential and other decaying terms (b < 0) with a diffuse
+    pair Gaussian (xi = 0.02, so that b / sqrt(xi) ~ -8): the integrand of
+    Eq. (bfinal) peaks at (2 xi R + b) / (2 xi), below R or at r = 0, far
+    from the pair Gaussian's centre.  Oracle A_0..A_2 against mpmath's
+    adaptive quadrature of the same radial integral,
+      A_n / N' = int_0^inf r k(r) D^n g(r, R) dr,  g = [e^{-xi (r-R)^2} - e^{-xi (r+R)^2}] / R,
+    with breaks at the powers of two up to 128 and at R and 2R (the peaks of
+    these kernels lie below 1), and D^n g written out by hand.
+    Catches quadrature panels that miss a decaying term's peak (the formula
+    itself is pinned by the convolution quadrature above)."""
+    fac = TermFactor(GENERIC_FACTORS[fa])
+    xi = 0.02
+    R = math.sqrt(T / xi)
+    nmax = 2
+    A = radial.radial_auto(cls, [xi], [R], nmax, fac, fac).to_mp()[0]
+    with mp.workdps(40):
+        k = _kernel_mp(cls, fac, fac)
+        x = mp.mpf(xi)
+        pts = sorted({mp.mpf(0), mp.mpf(R), mp.mpf(2 * R)} | {mp.mpf(2) ** j for j in range(-3, 8)}) + [mp.inf]
+
+        Rm = mp.mpf(R)
+
+        def dn(r, n):
+            # g = h_- - h_+, h_s = e^{-xi (r + s R)^2} / R; with
+            # q_s = -2 xi s r / R - 2 xi - 1/R^2:  D h_s = h_s q_s,
+            # D^2 h_s = h_s (q_s^2 + q_s' / R),  q_s' = 2 xi s r / R^2 + 2 / R^3
+            v = mp.mpf(0)
+            for s_, sign in ((-1, 1), (1, -1)):
+                h = mp.exp(-x * (r + s_ * Rm) ** 2) / Rm
+                q = -2 * x * s_ * r / Rm - 2 * x - 1 / Rm ** 2
+                dq = 2 * x * s_ * r / Rm ** 2 + 2 / Rm ** 3
+                v += sign * h * (1 if n == 0 else (q if n == 1 else q * q + dq / Rm))
+            return v
+
+        ref = [mp.quad(lambda r: r * k(r) * dn(r, n), pts) for n in range(nmax + 1)]
+    sc = [(2 * xi) ** n for n in range(nmax + 1)]
+    env = max(abs(ref[n]) / sc[n] for n in range(nmax + 1))
+    for n in range(nmax + 1):
         err = abs(A[n] - ref[n]) / sc[n] / env
         assert err < 1e-16, (n, A[n], ref[n], err)
 
