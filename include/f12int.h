@@ -311,6 +311,31 @@ void f12_batch_destroy(f12_batch *b);
  * Asynchronous on `stream`. */
 int f12_aux_radial(const f12_kernel *k, int64_t n, const double *d_p, const double *d_q,
                    const double *d_R, int32_t L, int32_t route, double *d_A, void *stream);
+/* ------------------------------------------------- solid harmonics ---- */
+/* Output over real solid harmonics, the basis of the spherical tensor
+ * gradient operators Y_lm(nabla) of Eq. (Ylm) (Sec. II.D): each index of a
+ * Cartesian block [a][b][c][d] goes over to S_lm, m = -l..l, with
+ * S_lm(r) = sqrt(4 pi/(2l+1)) r^l Y_lm(r^) in real form (Racah's
+ * normalisation: S_l0 = z^l + ..., S_11 = x, S_1-1 = y, S_22 =
+ * sqrt(3)/2 (x^2 - y^2)), so a shell of unnormalised primitives
+ * x^i y^j z^k exp(-e r^2) becomes S_lm(r) exp(-e r^2).
+ * f12_sph_coefficients: host double[(2l+1) * (l+1)(l+2)/2], row m + l, column
+ * the Cartesian component in canonical order (i from l down, then j from
+ * l - i down); 0 <= l <= 3 (else F12_EINVAL). */
+int f12_sph_coefficients(int32_t l, double *out);
+/* Offsets of the spherical blocks in the list's public order: host
+ * int64[n_quartets + 1], block q of (2l_a+1)(2l_b+1)(2l_c+1)(2l_d+1) doubles. */
+int f12_quartet_offsets_sph(const f12_quartets *q, int64_t *offsets);
+/* Enqueues on `stream` the transform of the Cartesian blocks [q_begin, q_end)
+ * at d_cart (laid out as f12_eval writes the range: block q at
+ * d_cart + offsets[q] - offsets[q_begin]) into spherical blocks at
+ * d_sph + sph_offsets[q] - sph_offsets[q_begin], [ma][mb][mc][md] with m
+ * ascending.  Device pointers; the two buffers must not overlap.
+ * F12_EBUFSIZE if sph_capacity cannot hold the range; F12_EINVAL for bad
+ * arguments. */
+int f12_cart_to_sph(const f12_quartets *q, int64_t q_begin, int64_t q_end, const double *d_cart,
+                    double *d_sph, int64_t sph_capacity, void *stream);
+
 /* Host-side table builder: W_a(x) = R int_0^inf t^a exp(-(t-x)^2) dt
  * (Eq. (sila) with beta = 2x, gamma = 1, times exp(-x^2)) for
  * a = alpha0 + m, m = m_lo..m_hi (alpha0 in [0,1); is_int = 1 for alpha0 = 0

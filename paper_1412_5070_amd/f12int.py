@@ -70,6 +70,9 @@ EXPORTS = {
     "f12_aux_radial": (_c_i32, [_vp, _c_i64, _vp, _vp, _vp, _c_i32, _c_i32, _vp, _vp]),
     "f12_aux_w_column": (_c_i32, [_c_dbl, _c_i32, _c_i32, _c_i32, _c_dbl, _P(_c_dbl)]),
     "f12_stream_status": (_c_i32, [_vp]),
+    "f12_sph_coefficients": (_c_i32, [_c_i32, _P(_c_dbl)]),
+    "f12_quartet_offsets_sph": (_c_i32, [_vp, _P(_c_i64)]),
+    "f12_cart_to_sph": (_c_i32, [_vp, _c_i64, _c_i64, _vp, _vp, _c_i64, _vp]),
     "f12_strerror": (ctypes.c_char_p, [_c_i32]),
 }
 for _name, (_res, _args) in EXPORTS.items():
@@ -314,6 +317,31 @@ def eval_sets(quartets, kernels, out, q_begin=0, q_end=None, stream=None):
 
 FP64, SPLIT_FP32 = 0, 1
 ENONFINITE = -7
+
+
+def sph_coefficients(l):
+    """f12_sph_coefficients: (2l+1, ncart(l)) matrix of the real solid harmonics."""
+    nc = (l + 1) * (l + 2) // 2
+    out = np.zeros((2 * l + 1) * nc)
+    _check(_lib.f12_sph_coefficients(int(l), _dptr(out)), "f12_sph_coefficients")
+    return out.reshape(2 * l + 1, nc)
+
+
+def offsets_sph(quartets):
+    o = np.zeros(quartets.n_quartets + 1, dtype=np.int64)
+    _check(_lib.f12_quartet_offsets_sph(quartets.handle, o.ctypes.data_as(_P(_c_i64))), "f12_quartet_offsets_sph")
+    return o
+
+
+def cart_to_sph(quartets, cart, out, q_begin=0, q_end=None, stream=None):
+    """Enqueue f12_cart_to_sph: Cartesian blocks (as eval_into writes them) to solid-harmonic blocks."""
+    import torch
+    if q_end is None:
+        q_end = quartets.n_quartets
+    assert cart.dtype == torch.float64 and cart.is_cuda and out.dtype == torch.float64 and out.is_cuda
+    _check(_lib.f12_cart_to_sph(quartets.handle, int(q_begin), int(q_end), _vp(cart.data_ptr()),
+                                _vp(out.data_ptr()), out.numel(), _stream_ptr(stream)), "f12_cart_to_sph")
+    return out
 
 
 def eval_precision(quartets, kernel, out, precision, q_begin=0, q_end=None, stream=None):
