@@ -225,6 +225,19 @@ typedef enum {
 int f12_eval_sets(f12_quartets *q, const f12_kernel *const *kernels, int32_t nset, int64_t q_begin,
                   int64_t q_end, double *d_out, int64_t out_capacity, void *stream);
 
+/* First derivatives (Sec. II.B: E and F = dE/d(A - B), and the shift of the
+ * Hermite Gaussians with P = (aA + bB)/p): blocks of d/dA_dir (ab|k|cd),
+ * A the centre of the bra's first shell, dir 0/1/2 = x/y/z, laid out as
+ * f12_eval lays out the integrals.  The other centres follow from the
+ * symmetries of I1-I4 and I6: d/dB of (ab|cd) is d/dA of (ba|cd) (block
+ * transposed in a, b), d/dC and d/dD are d/dA and d/dB of (cd|ab), and
+ * d/dA + d/dB + d/dC + d/dD = 0.  I1-I4 and I6 (else F12_EINVAL, as for a bad
+ * dir); F12_ELMAX for a range holding shapes with l_a + l_b = 6 and
+ * l_c + l_d = 6, whose derivative form does not fit the LDS; otherwise as
+ * f12_eval. */
+int f12_eval_grad(f12_quartets *q, const f12_kernel *k, int32_t dir, int64_t q_begin, int64_t q_end,
+                  double *d_out, int64_t out_capacity, void *stream);
+
 /* f12_eval with the contraction arithmetic chosen by `precision`
  * (F12_FP64 gives exactly f12_eval's result).  F12_EINVAL for an unknown
  * precision; otherwise as f12_eval. */

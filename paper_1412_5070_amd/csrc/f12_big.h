@@ -26,6 +26,13 @@
 // gradient coefficient -1) runs four ket transforms:
 //   comp 0: (a-b)/(2p) E^ab with R_lap = R_{t+2,u,v} + R_{t,u+2,v} + R_{t,u,v+2},
 //   comp d: -F^ab_d with R shifted by one along d.
+// MODE 3: the first derivative of I1-I4, I6 with respect to the bra's first
+// centre along direction d = a.gdir.  With P = (a A + b B)/p and the Hermite
+// Gaussians Lambda_t(x - P_x) = (d/dP_x)^t e^{-p (x - P_x)^2},
+//   d/dA_x sum_t E_t Lambda_t = sum_t [F_t + (a/p) E_{t-1}] Lambda_t,
+// F = dE/d(A_x - B_x) (Sec. II.B): the bra coefficients along d become
+// G_t = F_t + (a/p) E_{t-1}, t <= i + j + 1, over one ket transform with the
+// bra Hermite range l_a + l_b + 1.
 #pragma once
 #include <type_traits>
 
@@ -58,6 +65,16 @@ constexpr int max_nf(int lcd) {
   return hs3c(lcd) - hs3c(lcmin - 1);
 }
 
+// MODE 3: the G table of one direction, t <= l_a + l_b + 1.
+constexpr int max_eabg(int lab) {
+  int m = 0;
+  for (int la = 0; la <= LMAX; ++la) {
+    const int lb = lab - la;
+    if (lb >= 0 && lb <= LMAX) m = cmax(m, (la + 1) * (lb + 1) * (lab + 2));
+  }
+  return m;
+}
+
 // Bra E tables up to (l_a + 2, l_b + 2) and the D tables of MODE 2.
 constexpr int max_eab2(int lab) {
   int m = 0;
@@ -69,11 +86,13 @@ constexpr int max_eab2(int lab) {
 }
 
 // MODE: 0 = I1-I4, I6; 1 = I5 by four components; 2 = I5 by the Laplacian
-// form, with LAB = l_a + l_b + 2 (the bra Hermite range of the ket transform).
+// form, with LAB = l_a + l_b + 2 (the bra Hermite range of the ket transform);
+// 3 = first derivative along a.gdir with respect to the bra's first centre,
+// LAB = l_a + l_b + 1.
 template <int LAB, int LCD, int MODE, int NJ>
 struct BigShape {
   static constexpr bool I5 = MODE == 1;
-  static constexpr int BLAB = MODE == 2 ? LAB - 2 : LAB;  // l_a + l_b
+  static constexpr int BLAB = MODE == 2 ? LAB - 2 : (MODE == 3 ? LAB - 1 : LAB);  // l_a + l_b
   static constexpr int NT = 256;
   static constexpr int LP = LAB + LCD;
   static constexpr int L = LP + (I5 ? 2 : 0);
@@ -89,7 +108,8 @@ struct BigShape {
   static constexpr int YST = NUV * NE;
   static constexpr int NZT = NLP * (LAB + 1);
   static constexpr int NYT = (LP + 1) * (LAB + 1) * (LCD + 1);
-  static constexpr int NEB = MODE == 2 ? max_eab2(BLAB) : (I5 ? 6 : 3) * max_eab(LAB);
+  static constexpr int NEB = MODE == 2 ? max_eab2(BLAB)
+                             : (MODE == 3 ? 6 * max_eab(BLAB) + max_eabg(BLAB) : (I5 ? 6 : 3) * max_eab(LAB));
   // LDS (doubles)
   // per ket primitive of a pass: G rows, Z, Y, one-centre E
   static constexpr int jG = 0;
@@ -399,6 +419,21 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
         if (j >= 2) v -= j * (j - 1) * E[(i * ESb + j - 2) * ESt + t];
         Fb[d * Dab1 + (i * (lb + 1) + j) * DSt + t] = 0.5 * v;
       }
+    } else if constexpr (MODE == 3) {
+      // E and F = dE/dAB up to (l_a, l_b), then G = F + (a/p) E_{t-1} along gdir
+      e_tables_wg(ea, eb, ABb[0], ABb[1], ABb[2], la, lb, Eb, Fb, Eab1, tid, NT);
+      const int GSt = BLAB + 2, ng = (la + 1) * (lb + 1) * GSt;
+      const double *E = Eb + a.gdir * Eab1, *F = Fb + a.gdir * Eab1;
+      double *G = Fb + 3 * Eab1;
+      const double ap = ea / pb;
+      for (int k = tid; k < ng; k += NT) {
+        const int t = k % GSt, ij = k / GSt;
+        const int i = ij / (lb + 1), j = ij - i * (lb + 1);
+        double v = 0.0;
+        if (t <= i + j) v = F[(i * (lb + 1) + j) * ESt + t];
+        if (t >= 1 && t - 1 <= i + j) v += ap * E[(i * (lb + 1) + j) * ESt + t - 1];
+        G[k] = v;
+      }
     } else {
       e_tables_wg(ea, eb, ABb[0], ABb[1], ABb[2], la, lb, Eb, I5 ? Fb : nullptr, Eab1, tid, NT);
     }
@@ -674,7 +709,19 @@ __global__ void __launch_bounds__(256) big_kernel(ContractArgs a) {
           cart_comp(la, ab / nb, ax, ay, az);
           cart_comp(lb, ab % nb, bx, by, bz);
           double sacc = 0.0;
-          if constexpr (MODE == 2) {
+          if constexpr (MODE == 3) {
+            // E along the other directions (stride l_a + l_b + 1), G along gdir
+            const int GSt = BLAB + 2, g = a.gdir;
+            const double *Gb = Fb + 3 * Eab1;
+            const int ia[3] = {ax, ay, az}, ib[3] = {bx, by, bz};
+            const double *er[3];
+            int nn[3];
+            for (int d = 0; d < 3; ++d) {
+              er[d] = d == g ? Gb + (ia[d] * (lb + 1) + ib[d]) * GSt : Eb + d * Eab1 + (ia[d] * (lb + 1) + ib[d]) * ESt;
+              nn[d] = ia[d] + ib[d] + (d == g ? 1 : 0);
+            }
+            sacc = box(er[0], er[1], er[2], nn[0], nn[1], nn[2], f);
+          } else if constexpr (MODE == 2) {
             const double *er[3] = {Eb + (ax * ESb + bx) * ESt, Eb + Eab1 + (ay * ESb + by) * ESt,
                                    Eb + 2 * Eab1 + (az * ESb + bz) * ESt};
             const double *dr[3] = {Fb + (ax * (lb + 1) + bx) * DSt, Fb + Dab1 + (ay * (lb + 1) + by) * DSt,
@@ -745,10 +792,28 @@ constexpr bool lap_fits() {
   return S::BYTES <= 160 * 1024 && S::MAXW <= 40 && S::MAXU <= 32;
 }
 
+// The derivative form (MODE 3) where its LDS and register slots fit: every
+// shape but those with l_a + l_b = 6 and l_c + l_d = 6.
+template <int LAB, int LCD>
+constexpr bool grad_fits() {
+  using S = BigShape<LAB + 1, LCD, 3, 1>;
+  return S::BYTES <= 160 * 1024 && S::MAXW <= 40 && S::MAXU <= 32;
+}
+
+// -3: the shape has no derivative form (F12_ELMAX at the boundary)
+template <int LAB, int LCD, int PREC>
+inline int launch_big_grad(const ContractArgs &a, unsigned nblocks, hipStream_t st) {
+  if constexpr (PREC == 0 && grad_fits<LAB, LCD>())
+    return launch_big_t<LAB + 1, LCD, 3, PREC>(a, nblocks, st);
+  else
+    return -3;
+}
+
 template <int LAB, int PREC>
 inline int launch_big_lab(int lcd, int i5, const ContractArgs &a, unsigned nblocks, hipStream_t st) {
 #define F12_BIG_CASE(LCD)                                                                       \
   case LCD:                                                                                     \
+    if (a.gdir >= 0) return launch_big_grad<LAB, LCD, PREC>(a, nblocks, st);                    \
     if (!i5) return launch_big_t<LAB, LCD, 0, PREC>(a, nblocks, st);                            \
     if constexpr (lap_fits<LAB, LCD>()) return launch_big_t<LAB + 2, LCD, 2, PREC>(a, nblocks, st); \
     else return launch_big_t<LAB, LCD, 1, PREC>(a, nblocks, st);

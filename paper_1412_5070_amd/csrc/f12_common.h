@@ -129,6 +129,7 @@ struct ContractArgs {
   int64_t out_base;
   int prec;    // 0: FP64; 1: ket transform in split FP32
   int *fault;  // the device's fault word (set on a non-finite output element)
+  int gdir;    // -1: the integrals; 0, 1, 2: d/dA_x, d/dA_y, d/dA_z of them
 };
 
 // Position of one-centre component (fx, fy, fz) among |f| = l_c .. l_c+l_d.

@@ -1011,7 +1011,7 @@ int finish_quartets(f12_quartets *Q, std::vector<int64_t> &qb, std::vector<int64
 // Evaluates [q_begin, q_end) with radial-derivative scratch A of cap_prims
 // primitive quartets (times LTOT_MAX + 1 doubles), in chunks that fit it.
 int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_end, double *d_out,
-               double *A, int64_t cap_prims, hipStream_t st, int prec = 0);
+               double *A, int64_t cap_prims, hipStream_t st, int prec = 0, int gdir = -1);
 
 }  // namespace
 
@@ -1350,14 +1350,14 @@ extern "C" void f12_quartets_destroy(f12_quartets *q) { delete q; }
 namespace {
 
 int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_end, double *d_out,
-               double *A, int64_t cap_prims, hipStream_t st, int prec) {
+               double *A, int64_t cap_prims, hipStream_t st, int prec, int gdir) {
   const PairsDev bra = Q->bra->dev(), ket = Q->ket->dev();
   const int i5 = (Q->cls == 5);
   const int64_t out_base = Q->qoff[q_begin];
   for (const Bin &b : Q->bins) {
     int64_t lo = std::max(b.q0, q_begin), hi = std::min(b.q0 + b.nq, q_end);
     if (lo >= hi) continue;
-    const int L = b.la + b.lb + b.lc + b.ld + (i5 ? 2 : 0);
+    const int L = b.la + b.lb + b.lc + b.ld + (i5 ? 2 : 0) + (gdir >= 0 ? 1 : 0);
     int64_t qa = lo;
     while (qa < hi) {
       // largest chunk [qa, qe) with at most cap_prims primitive quartets
@@ -1372,7 +1372,7 @@ int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_
         return F12_EDEVICE;
       if (launch_contract(bra, ket, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qoff.ptr, Q->d_qprim.ptr, qa,
                           qe - qa, p0, np, A, b.la, b.lb, b.lc, b.ld, i5, d_out, out_base,
-                          st, 0, prec) != 0)
+                          st, 0, prec, gdir) != 0)
         return F12_EDEVICE;
       qa = qe;
     }
@@ -1409,6 +1409,25 @@ extern "C" int f12_eval_sets(f12_quartets *q, const f12_kernel *const *kernels, 
     if (st) return st;
   }
   return F12_OK;
+}
+
+extern "C" int f12_eval_grad(f12_quartets *q, const f12_kernel *k, int32_t dir, int64_t q_begin,
+                             int64_t q_end, double *d_out, int64_t out_capacity, void *stream) {
+  if (!q || !k || !d_out || q_begin < 0 || q_end > q->nq || q_begin > q_end) return F12_EINVAL;
+  if (k->cls != q->cls || q->cls == 5 || dir < 0 || dir > 2) return F12_EINVAL;
+  if (q->qoff[q_end] - q->qoff[q_begin] > out_capacity) return F12_EBUFSIZE;
+  if (q_begin == q_end) return F12_OK;
+  // every shape of the range must have a derivative form (checked before any launch)
+  const PairsDev bra = q->bra->dev(), ket = q->ket->dev();
+  for (const Bin &b : q->bins) {
+    if (std::max(b.q0, q_begin) >= std::min(b.q0 + b.nq, q_end)) continue;
+    const int s = launch_contract(bra, ket, nullptr, nullptr, nullptr, nullptr, 0, 1, 0, 0, nullptr, b.la, b.lb,
+                                  b.lc, b.ld, 0, nullptr, 0, (hipStream_t)stream, -1, 0, (int)dir);
+    if (s == -3) return F12_ELMAX;
+    if (s != 0) return F12_EDEVICE;
+  }
+  q->stage_qa = q->stage_qe = -1;
+  return eval_range(q, k, q_begin, q_end, d_out, q->d_A.ptr, q->a_cap_prims, (hipStream_t)stream, 0, (int)dir);
 }
 
 extern "C" int f12_eval_precision(f12_quartets *q, const f12_kernel *k, int64_t q_begin, int64_t q_end,

@@ -870,9 +870,11 @@ static int launch_big(int lab, int lcd, int i5, const ContractArgs &a, unsigned 
 int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb, const int64_t *qk,
                     const int64_t *qoff, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
                     int64_t np, const double *A, int la, int lb, int lc, int ld, int i5,
-                    double *out, int64_t out_base, hipStream_t stream, int64_t grid, int prec) {
+                    double *out, int64_t out_base, hipStream_t stream, int64_t grid, int prec,
+                    int gdir) {
   if (nqc <= 0) return 0;
   ContractArgs a;
+  a.gdir = gdir;
   a.fault = fault_word();
   if (!a.fault) return -1;
   a.bra = bra;

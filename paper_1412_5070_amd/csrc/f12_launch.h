@@ -20,7 +20,7 @@ int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
                     const int64_t *qoff, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
                     int64_t np, const double *A, int la, int lb, int lc, int ld, int i5,
                     double *out, int64_t out_base, hipStream_t stream, int64_t grid = 0,
-                    int prec = 0);
+                    int prec = 0, int gdir = -1);
 
 // Device address of the current device's fault word (looked up once per
 // device; nullptr if the lookup fails).  Kernels set the word to 1 when they

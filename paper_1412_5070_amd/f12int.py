@@ -58,6 +58,7 @@ EXPORTS = {
     "f12_eval": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp]),
     "f12_eval_precision": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i32, _vp]),
     "f12_eval_sets": (_c_i32, [_vp, _P(_vp), _c_i32, _c_i64, _c_i64, _vp, _c_i64, _vp]),
+    "f12_eval_grad": (_c_i32, [_vp, _vp, _c_i32, _c_i64, _c_i64, _vp, _c_i64, _vp]),
     "f12_eval_noalloc": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _vp]),
     "f12_eval_stage": (_c_i32, [_vp, _vp, _c_i64, _c_i64, _vp, _c_i64, _c_i32, _vp]),
     "f12_quartets_scratch_prims": (_c_i32, [_vp, _P(_c_i64)]),
@@ -300,6 +301,17 @@ def eval_into(quartets, kernel, out, q_begin=0, q_end=None, stream=None):
     assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
     _check(_lib.f12_eval(quartets.handle, kernel.handle, int(q_begin), int(q_end), _vp(out.data_ptr()),
                          out.numel(), _stream_ptr(stream)), "f12_eval")
+    return out
+
+
+def eval_grad(quartets, kernel, direction, out, q_begin=0, q_end=None, stream=None):
+    """Enqueue f12_eval_grad: d/dA_direction of the blocks (A the bra's first centre)."""
+    import torch
+    if q_end is None:
+        q_end = quartets.n_quartets
+    assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+    _check(_lib.f12_eval_grad(quartets.handle, kernel.handle, int(direction), int(q_begin), int(q_end),
+                              _vp(out.data_ptr()), out.numel(), _stream_ptr(stream)), "f12_eval_grad")
     return out
 
 

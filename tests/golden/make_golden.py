@@ -156,6 +156,11 @@ FACTOR_CASES = [(2, "P2", "P2"), (3, "P2", "P2"), (5, "P2", "P2"), (2, "P4", "P4
                 (4, "P4", "P4"), (5, "P4", "P4"), (6, "P4", "P4"), (4, "P1", "P4"), (6, "P1", "P4")]
 FACTOR_QUADS = [(0, 0, 0, 0), (1, 0, 2, 3), (3, 1, 4, 2), (3, 3, 5, 1)]
 
+# first derivatives d/dA of the s-f molecule's blocks ([3][block] per quartet):
+# every shape but (ff|ff), whose derivative form the library does not build
+GRAD_QUADS = [(6, 2, 10, 6), (3, 2, 7, 5), (0, 0, 7, 11), (11, 7, 0, 4), (9, 3, 2, 8), (10, 1, 4, 7),
+              (5, 0, 9, 4), (1, 1, 1, 1)]
+
 
 # negative powers in the kernel terms: P3 (rho = -3, n = 2) in every class,
 # P2 (rho = -3/2) in I4 and I6 (rho + rho' = -3)
@@ -181,6 +186,10 @@ def _job(args):
         sh = [tiny_config()[1][i].as_dict() for i in quad]
         return args, np.asarray(integrals.contracted(cls, *sh, FACTOR_SETS[f], FACTOR_SETS[fp]),
                                 dtype=np.float64).ravel()
+    if setname == "grad":
+        from oracle.gradient import grad_first_centre
+        sh = [df3_shells()[i].as_dict() for i in quad]
+        return args, np.asarray(grad_first_centre(cls, *sh, P1, P1), dtype=np.float64).ravel()
     if setname == "tinyall":
         from synth import tiny_config
         shells = tiny_config()[1]
@@ -211,6 +220,8 @@ def build(setname):
         jobs = [(setname, c, q) for c in (5, 2, 3, 4, 6) for q in quads]
     elif setname == "generic":
         jobs = [(setname, c, q, "G5", "G5") for c in (5, 2, 3, 4, 6) for q in FACTOR_QUADS]
+    elif setname == "grad":
+        jobs = [(setname, c, q) for c in (2, 3, 4, 6) for q in GRAD_QUADS]
     elif setname == "stg":
         jobs = [(setname, c, q, f, f) for f in ("STG", "STG3") for c in (5, 2, 3, 4, 6) for q in FACTOR_QUADS]
     elif setname in ("factors", "negpow"):
