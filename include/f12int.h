@@ -349,6 +349,18 @@ int f12_quartet_offsets_sph(const f12_quartets *q, int64_t *offsets);
 int f12_cart_to_sph(const f12_quartets *q, int64_t q_begin, int64_t q_end, const double *d_cart,
                     double *d_sph, int64_t sph_capacity, void *stream);
 
+/* Hermite integrals R_tuv by the Hobson / spherical-tensor route of
+ * Sec. II.D, Eq. (Ylm), with the powers of the Laplacian that Eq. (QxQyQz)
+ * leaves out restored: R_tuv = sum c_{tuv,lm} S_lm(X) [D^l (nabla^2)^k B](X),
+ * N = t+u+v = l + 2k, nabla^2 = 3D + |X|^2 D^2 on radial functions; an
+ * alternative to the MD recurrence that the contraction kernels use (a
+ * diagnostic path).  Device arrays: d_A[np][L+1] radial derivatives
+ * A_n = D^n B, d_X[np][3] the vectors X = Q - P, d_R[np][(L+1)(L+2)(L+3)/6]
+ * in the Hermite order (by N, then t descending, then u descending).
+ * 0 <= L <= 14 (else F12_EINVAL). */
+int f12_hermite_hobson(const double *d_A, const double *d_X, int64_t np, int32_t L, double *d_R,
+                       void *stream);
+
 /* Host-side table builder: W_a(x) = R int_0^inf t^a exp(-(t-x)^2) dt
  * (Eq. (sila) with beta = 2x, gamma = 1, times exp(-x^2)) for
  * a = alpha0 + m, m = m_lo..m_hi (alpha0 in [0,1); is_int = 1 for alpha0 = 0

@@ -74,6 +74,7 @@ EXPORTS = {
     "f12_sph_coefficients": (_c_i32, [_c_i32, _P(_c_dbl)]),
     "f12_quartet_offsets_sph": (_c_i32, [_vp, _P(_c_i64)]),
     "f12_cart_to_sph": (_c_i32, [_vp, _c_i64, _c_i64, _vp, _vp, _c_i64, _vp]),
+    "f12_hermite_hobson": (_c_i32, [_vp, _vp, _c_i64, _c_i32, _vp, _vp]),
     "f12_strerror": (ctypes.c_char_p, [_c_i32]),
 }
 for _name, (_res, _args) in EXPORTS.items():
@@ -337,6 +338,17 @@ def sph_coefficients(l):
     out = np.zeros((2 * l + 1) * nc)
     _check(_lib.f12_sph_coefficients(int(l), _dptr(out)), "f12_sph_coefficients")
     return out.reshape(2 * l + 1, nc)
+
+
+def hermite_hobson(A, X, L, stream=None):
+    """f12_hermite_hobson: R_tuv (Hermite order) from A (np, L+1) and X (np, 3), CUDA float64."""
+    import torch
+    A = A.contiguous(); X = X.contiguous()
+    np_ = A.shape[0]
+    R = torch.empty((np_, (L + 1) * (L + 2) * (L + 3) // 6), dtype=torch.float64, device=A.device)
+    _check(_lib.f12_hermite_hobson(_vp(A.data_ptr()), _vp(X.data_ptr()), np_, int(L), _vp(R.data_ptr()),
+                                   _stream_ptr(stream)), "f12_hermite_hobson")
+    return R
 
 
 def offsets_sph(quartets):
