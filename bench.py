@@ -46,16 +46,16 @@ METRIC = "contracted shell-quartets/s per F12 class at ≤1e-12 rel err; % FP64 
 KERNEL_SOURCES = ["f12_big.h", "f12_common.h", "f12_launch.h", "f12_internal.h", "f12_kernels.hip",
                   "f12_dd.h", "f12_big_unit.hip"]
 TRAFFIC_RECORD = {
-    "sources_sha1": "176023899205a1c8c032d67df419661d2421f6c2",
+    "sources_sha1": "1440ae3c3fbc90594e905edbd8054ad7f2af2e7c",
     "fetch_scale": 1048576 / 524299.5,
     "write_scale": 1.0,
-    "contraction_bytes_per_launch": 6.44345e7 + 7.92805e7,
-    "aux_bytes_per_launch": 7.38886e8 + 1.39116e9,
+    "contraction_bytes_per_launch": 6.43211e+07 + 7.82614e+07,
+    "aux_bytes_per_launch": 7.34461e+08 + 1.38934e+09,
     # FP64 flops issued per launch, 64 lanes x (2 SQ_INSTS_VALU_FMA_F64 + SQ_INSTS_VALU_MUL_F64 +
     # SQ_INSTS_VALU_ADD_F64), from one more --pmc pass (profiles/contraction_fp64_counters.md);
     # an upper bound, since lanes masked off are counted too
-    "contraction_hw_fp64_flops_per_launch": 3.117e10,
-    "aux_hw_fp64_flops_per_launch": 1.095e10,
+    "contraction_hw_fp64_flops_per_launch": 3.128e+10,
+    "aux_hw_fp64_flops_per_launch": 1.095e+10,
 }
 
 
