@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (256 CUs x 2.4 GHz x 128 flop/clk)
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 CLASSES = (2, 3, 4, 5, 6)
 METRIC = "contracted shell-quartets/s per F12 class at ≤1e-12 rel err; % FP64 peak"
 
@@ -702,6 +703,8 @@ def main():
     ap.add_argument("--slices", type=int, default=64, help="batched: steps that cover the whole job")
     ap.add_argument("--branches", type=int, default=4, help="batched: concurrent branches of each graph")
     ap.add_argument("--tune-file", default=None, help="batched: tuning results to read and update")
+    ap.add_argument("--chunk-log", default=None, metavar="FILE",
+                    help="write one JSON line per timed output chunk (class, batch, quartet range, digest)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (three times) and exit: "
                          "the reference reading that scales the HBM byte counters")
@@ -833,6 +836,17 @@ def main():
                 f12int.eval_stage(Qi, kern, out, s0, s1, 2, st)
                 e1.record(st)
                 done[i % 2] = e1
+                # the chunk's checksum (read back after the timed steps)
+                if record is not None:
+                    slot = len(record["chunks"])
+                    dslot = digests[slot:slot + 1]
+                else:
+                    dslot = digest_sink
+                ed1 = torch.cuda.Event(enable_timing=True)
+                f12int.digest(Qi, out, dslot, s0, s1, st)
+                ed1.record(st)
+                if record is not None:
+                    record["chunks"].append((wk["cls"], batch, s0, s1, e1, ed1, 8 * size))
                 if record is not None:
                     record["aux"].append((ea, ea_end))
                 nq += s1 - s0
@@ -857,11 +871,17 @@ def main():
         torch.cuda.synchronize()
         log("batch %d: all classes done" % batch)
 
+    # one 64-bit digest per timed output chunk (f12_digest adds into its slot)
+    n_chunks = sum(1 for s in range(args.steps) for wk in work
+                   for _ in slices(wk, (args.warmup + s) % args.batches))
+    digests = torch.zeros(max(n_chunks, 1), dtype=torch.int64, device="cuda")
+    digest_sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+
     for w in range(args.warmup):
         run_step(w % args.batches, None)
     torch.cuda.synchronize()
     f12int.stream_status()
-    rec = {"launches": [], "classes": [], "aux": [], "aux_flops": []}
+    rec = {"launches": [], "classes": [], "aux": [], "aux_flops": [], "chunks": []}
     t0 = time.perf_counter()
     nq_total = 0
     for s in range(args.steps):
@@ -897,6 +917,22 @@ def main():
     aux_time = sum(a.elapsed_time(b) / 1e3 for (a, b) in rec["aux"])
     aux_fl = float(sum(rec["aux_flops"]))
     gpu_time = sum(v[1] for v in per_class.values())
+
+    # chunk digests: per class the sum mod 2^64 (equal to the digest of all the
+    # class's timed blocks); the digest launch is timed from the end of the
+    # contraction that wrote the chunk to its own end
+    dg = digests[:len(rec["chunks"])].cpu().numpy().view(np.uint64)
+    per_class_digest = {}
+    for (cls, _, _, _, _, _, _), v in zip(rec["chunks"], dg):
+        per_class_digest[cls] = (per_class_digest.get(cls, 0) + int(v)) % 2 ** 64
+    dig_time = sum(a.elapsed_time(b) / 1e3 for (_, _, _, _, a, b, _) in rec["chunks"])
+    dig_bytes = sum(nb for (_, _, _, _, _, _, nb) in rec["chunks"])
+    big = [(a.elapsed_time(b) / 1e3, nb) for (_, _, _, _, a, b, nb) in rec["chunks"] if nb >= 32 << 20]
+    if args.chunk_log:
+        with open(args.chunk_log, "w") as fh:
+            for (cls, batch, s0, s1, _, _, nb), v in zip(rec["chunks"], dg):
+                fh.write(json.dumps({"class": "I%d" % cls, "batch": batch, "q_begin": s0, "q_end": s1,
+                                     "doubles": nb // 8, "digest": "%016x" % int(v)}) + "\n")
 
     log("stored oracle sample")
     accuracy = stored_sample_errors(work, shells)
@@ -986,6 +1022,21 @@ def main():
                                           % AUX_START_FLOPS,
                            "hardware_fp64_achieved": None if not rec_ok else
                            TRAFFIC_RECORD["aux_hw_fp64_flops_per_launch"] / (aux_time / max(len(rec["aux"]), 1)) / 1e12},
+        },
+        "output_digest": {
+            "kernel": "chunk checksum (f12_digest), one launch per output chunk",
+            "per_class": {"I%d" % c: "%016x" % v for c, v in sorted(per_class_digest.items())},
+            "chunks": len(rec["chunks"]),
+            "avg_launch_ms": dig_time / max(len(rec["chunks"]), 1) * 1e3,
+            "bytes_per_launch": dig_bytes / max(len(rec["chunks"]), 1),
+            "achieved_GBps": dig_bytes / max(dig_time, 1e-30) / 1e9,
+            "frac_of_hbm_peak": dig_bytes / max(dig_time, 1e-30) / 1e9 / HBM_PEAK_GBPS,
+            "share_of_gpu_time": dig_time / gpu_time,
+            "chunks_of_32MiB_or_more": {
+                "chunks": len(big),
+                "achieved_GBps": sum(nb for _, nb in big) / max(sum(t for t, _ in big), 1e-30) / 1e9,
+                "frac_of_hbm_peak": sum(nb for _, nb in big) / max(sum(t for t, _ in big), 1e-30) / 1e9
+                                    / HBM_PEAK_GBPS},
         },
         "accuracy_vs_stored_oracle": accuracy,
         "cpu_baseline": cpu,

@@ -349,6 +349,23 @@ int f12_quartet_offsets_sph(const f12_quartets *q, int64_t *offsets);
 int f12_cart_to_sph(const f12_quartets *q, int64_t q_begin, int64_t q_end, const double *d_cart,
                     double *d_sph, int64_t sph_capacity, void *stream);
 
+/* Checksum of output chunks for streamed runs (the integrals of a long run
+ * are written to a ring buffer chunk by chunk and cannot all be kept; each
+ * chunk's quartet range and digest are logged instead, so that two runs can be
+ * compared and a run restarted at a chunk).  Adds to *d_digest, modulo 2^64,
+ *   D = sum_e mix(bits(x_e) + G (e0 + e + 1)),
+ * over the doubles x_e of blocks [q_begin, q_end) at d_out (laid out as
+ * f12_eval writes the range), e0 = offsets[q_begin] the global element index
+ * of the first one (f12_quartet_offsets), bits() the IEEE-754 bit pattern,
+ * G = 0x9E3779B97F4A7C15 and mix the SplitMix64 output function (Steele, Lea
+ * and Flood, OOPSLA 2014).  The sum does not depend on the order of
+ * reduction, and the digests of the parts of a split range add up to the
+ * digest of the whole.  d_digest: device uint64, set by the caller (to 0 for a
+ * fresh digest); d_out may be NULL for an empty range.  Enqueued on `stream`;
+ * F12_EINVAL for a bad range. */
+int f12_digest(const f12_quartets *q, int64_t q_begin, int64_t q_end, const double *d_out, uint64_t *d_digest,
+               void *stream);
+
 /* Hermite integrals R_tuv by the Hobson / spherical-tensor route of
  * Sec. II.D, Eq. (Ylm), with the powers of the Laplacian that Eq. (QxQyQz)
  * leaves out restored: R_tuv = sum c_{tuv,lm} S_lm(X) [D^l (nabla^2)^k B](X),

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libf12int.so")
 # (source, object name, extra defines)
-SOURCES = [(s, os.path.splitext(s)[0], []) for s in ("f12_host.cpp", "f12_batch.cpp", "f12_kernels.hip", "f12_k2.hip", "f12_sph.hip", "f12_hobson.hip")]
+SOURCES = [(s, os.path.splitext(s)[0], []) for s in ("f12_host.cpp", "f12_batch.cpp", "f12_kernels.hip", "f12_k2.hip", "f12_sph.hip", "f12_hobson.hip", "f12_digest.hip")]
 SOURCES += [("f12_big_unit.hip", "f12_big_unit_%d_%d" % (lab, prec), ["-DF12_LAB=%d" % lab, "-DF12_PREC=%d" % prec])
             for prec in (0, 1) for lab in range(7)]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -75,6 +75,7 @@ EXPORTS = {
     "f12_quartet_offsets_sph": (_c_i32, [_vp, _P(_c_i64)]),
     "f12_cart_to_sph": (_c_i32, [_vp, _c_i64, _c_i64, _vp, _vp, _c_i64, _vp]),
     "f12_hermite_hobson": (_c_i32, [_vp, _vp, _c_i64, _c_i32, _vp, _vp]),
+    "f12_digest": (_c_i32, [_vp, _c_i64, _c_i64, _vp, _vp, _vp]),
     "f12_strerror": (ctypes.c_char_p, [_c_i32]),
 }
 for _name, (_res, _args) in EXPORTS.items():
@@ -366,6 +367,19 @@ def cart_to_sph(quartets, cart, out, q_begin=0, q_end=None, stream=None):
     _check(_lib.f12_cart_to_sph(quartets.handle, int(q_begin), int(q_end), _vp(cart.data_ptr()),
                                 _vp(out.data_ptr()), out.numel(), _stream_ptr(stream)), "f12_cart_to_sph")
     return out
+
+
+def digest(quartets, out, d_digest, q_begin=0, q_end=None, stream=None):
+    """Enqueue f12_digest: add the 64-bit digest of blocks [q_begin, q_end) in `out` (laid out as
+    eval_into writes the range) to the int64 CUDA scalar `d_digest` (wrapping, mod 2^64)."""
+    import torch
+    if q_end is None:
+        q_end = quartets.n_quartets
+    assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+    assert d_digest.dtype == torch.int64 and d_digest.is_cuda
+    _check(_lib.f12_digest(quartets.handle, int(q_begin), int(q_end), _vp(out.data_ptr()),
+                           _vp(d_digest.data_ptr()), _stream_ptr(stream)), "f12_digest")
+    return d_digest
 
 
 def eval_precision(quartets, kernel, out, precision, q_begin=0, q_end=None, stream=None):
