@@ -102,7 +102,7 @@ int run_chunk(const Chunk &c, const f12_kernel *k, double *A, int64_t grid, hipS
   const PairsDev bra = c.Q->bra->dev(), ket = c.Q->ket->dev();
   const int L = c.la + c.lb + c.lc + c.ld + (c.i5 ? 2 : 0);
   if (aux && launch_aux(k->d_desc.ptr, bra, ket, c.Q->d_qb.ptr, c.Q->d_qk.ptr, c.Q->d_qprim.ptr, c.qa,
-                        c.qe - c.qa, c.p0, c.np, L, A, st, k->host_desc.heavy) != 0)
+                        c.qe - c.qa, c.p0, c.np, L, A, st, aux_variant(k->host_desc)) != 0)
     return F12_EDEVICE;
   if (launch_contract(bra, ket, c.Q->d_qb.ptr, c.Q->d_qk.ptr, c.Q->d_qoff.ptr, c.Q->d_qprim.ptr, c.qa,
                       c.qe - c.qa, c.p0, c.np, A, c.la, c.lb, c.lc, c.ld, c.i5, c.out, c.out_base, st, grid) != 0)

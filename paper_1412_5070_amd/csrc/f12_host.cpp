@@ -830,6 +830,9 @@ int kernel_from_factors(int32_t cls, const Expr &ef, const Expr &efp, f12_kernel
   D.negb = 0;
   for (int c = 0; c < D.nchains; ++c)
     if (D.chains[c].b < 0.0) D.heavy = D.negb = 1;  // the downward ladders live in the heavy kernels
+  D.compact = !D.heavy;
+  for (int c = 0; c < D.nchains; ++c)
+    if (D.chains[c].m_max - D.chains[c].m_min > SPAN_C) D.compact = 0;
   // ---- W tables
   const int nx = (int)std::lround((WX_HI - WX_LO) * WX_INVH) + 1;
   for (size_t fi = 0; fi < fams.size(); ++fi) {
@@ -922,7 +925,8 @@ extern "C" int f12_aux_radial(const f12_kernel *k, int64_t n, const double *d_p,
   if (!k || n < 0 || L < 0 || L > LTOT_MAX || route < 0 || route > 3 ||
       (n > 0 && (!d_p || !d_q || !d_R || !d_A)))
     return F12_EINVAL;
-  if (launch_aux_points(k->d_desc.ptr, n, d_p, d_q, d_R, L, route, d_A, (hipStream_t)stream) != 0)
+  if (launch_aux_points(k->d_desc.ptr, n, d_p, d_q, d_R, L, route, d_A, (hipStream_t)stream,
+                        aux_variant(k->host_desc)) != 0)
     return F12_EDEVICE;
   return F12_OK;
 }
@@ -1368,7 +1372,7 @@ int eval_range(f12_quartets *Q, const f12_kernel *k, int64_t q_begin, int64_t q_
       const int64_t p0 = Q->qprim[qa];
       const int64_t np = Q->qprim[qe] - p0;
       if (launch_aux(k->d_desc.ptr, bra, ket, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qprim.ptr, qa,
-                     qe - qa, p0, np, L, A, st, k->host_desc.heavy) != 0)
+                     qe - qa, p0, np, L, A, st, aux_variant(k->host_desc)) != 0)
         return F12_EDEVICE;
       if (launch_contract(bra, ket, Q->d_qb.ptr, Q->d_qk.ptr, Q->d_qoff.ptr, Q->d_qprim.ptr, qa,
                           qe - qa, p0, np, A, b.la, b.lb, b.lc, b.ld, i5, d_out, out_base,
@@ -1457,7 +1461,7 @@ extern "C" int f12_eval_stage(f12_quartets *q, const f12_kernel *k, int64_t q_be
   if (stage == 1) {
     const int L = bin->la + bin->lb + bin->lc + bin->ld + (i5 ? 2 : 0);
     if (launch_aux(k->d_desc.ptr, bra, ket, q->d_qb.ptr, q->d_qk.ptr, q->d_qprim.ptr, q_begin,
-                   q_end - q_begin, p0, np, L, q->d_A.ptr, st, k->host_desc.heavy) != 0)
+                   q_end - q_begin, p0, np, L, q->d_A.ptr, st, aux_variant(k->host_desc)) != 0)
       return F12_EDEVICE;
     q->stage_qa = q_begin;
     q->stage_qe = q_end;

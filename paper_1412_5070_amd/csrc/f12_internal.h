@@ -16,6 +16,8 @@ constexpr int KPHI = 96;                // terms of the DD Phi-series (small-T r
 constexpr int NW_LIGHT = 32;            // the same bound for the common kernels
 constexpr int NW_MAX = 64;              // orders of W per chain in the large-T route:
                                         // (m_max - m_min) + LTOT_MAX + 1 must not exceed it
+constexpr int SPAN_C = 6;               // widest chain (m_max - m_min) of the register-resident
+                                        // large-T path (kernels that are not heavy)
 constexpr double WX_LO = -10.5;         // W-table abscissa range
 constexpr double WX_HI = 36.0;
 constexpr double WX_INVH = 64.0;        // grid step 1/64
@@ -52,6 +54,7 @@ struct KernelDev {
   int32_t heavy;   // negint, or a chain spanning more than NW_LIGHT orders in the large-T route
   int32_t singular;  // a term r^a with a <= -1 (finite parts; their singular pieces cancel across chains)
   int32_t negb;      // a decaying chain (b < 0)
+  int32_t compact;   // not heavy, and every chain spans at most SPAN_C orders
   ChainDesc chains[MAX_CHAINS];
   TermDesc terms[MAX_TERMS];
   FamilyDesc fam[MAX_FAMILIES];
@@ -62,6 +65,10 @@ struct KernelDev {
   // takes its place: F = (-1)^p psi(p + 1) / p!.
   const double *phi;
 };
+
+// Which radial-derivative kernel a launch takes: 1 heavy, 2 compact (orders
+// and arrays fixed at compile time per L), 0 the other light kernels.
+inline int aux_variant(const KernelDev &K) { return K.heavy ? 1 : (K.compact ? 2 : 0); }
 
 // Device-side pair data (structure of arrays).
 struct PairsDev {

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <math.h>
 #include <mutex>
+#include <utility>
 
 #include "f12_internal.h"
 #include "f12_common.h"
@@ -337,6 +338,196 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
     double pv = 0.0;
     for (int k = 0; k <= L - n; ++k) {
       double d = (k + 1) * gj[k + 1];
+      pv = (d - pv) * iR;
+      gj[k] = pv;
+    }
+    A[n] = gj[0];
+  }
+}
+
+// The large-T route of the common kernels (compact: not heavy, every chain
+// spanning at most SPAN_C orders) with L fixed at compile time: the same
+// formulas as aux_large<false>, arranged so that every array index is a
+// compile-time constant once the loops are unrolled, and the W orders, the
+// E-polynomials, phi and the R-jet stay in registers.  Orders are held for
+// m = m_min - L .. m_min - L + NO - 1 of each chain; those a chain does not
+// use are left at zero.
+__device__ __noinline__ double w_asym_call(double a, double X) { return w_asym(a, X); }
+
+template <int L>
+__device__ __forceinline__ void aux_large_c(const KernelDev *__restrict__ K, double xi, double R,
+                                            double mbudget, double (&A)[L + 1]) {
+  constexpr int NO = L + SPAN_C + 1;
+  double phi[L + 1];
+#pragma unroll
+  for (int m = 0; m <= L; ++m) phi[m] = 0.0;
+  const int nchains = K->nchains;
+  const double T = xi * R * R;
+  bool any_minus = false;
+  if (K->singular)
+    for (int c = 0; c < nchains; ++c) any_minus |= T * (xi / (xi + K->chains[c].g)) < mbudget;
+  for (int c = 0; c < nchains; ++c) {
+    const ChainDesc ch = K->chains[c];
+    const FamilyDesc F = K->fam[ch.family];
+    const double g = ch.g, b = ch.b;
+    const double gam = xi + g;
+    const double kap = xi / gam;
+    const double cs = b / (2.0 * gam);
+    const double a1 = b * kap;
+    const double a2 = xi * g / gam;
+    const double e0 = b * b / (4.0 * gam);
+    const double sqg = sqrt(gam);
+    const double isq = 1.0 / sqg;
+    const double g0 = pow(gam, -0.5 * (F.alpha0 + 1.0));
+    const int m0 = ch.m_min - L;  // order held in Om[0]
+    // orders below zero of an integer family with m_min >= 0 are not needed
+    const int ilo = (F.is_int && ch.m_min >= 0 && m0 < 0) ? -m0 : 0;
+    const int ihi = ch.m_max - m0;
+    // gam^{-(alpha0 + m + 1)/2} at m = m0
+    double gp0 = g0;
+    if (m0 >= 0) {
+      for (int i = 0; i < m0; ++i) gp0 *= isq;
+    } else {
+      for (int i = 0; i < -m0; ++i) gp0 *= sqg;
+    }
+    const bool do_minus = K->singular ? any_minus : kap * T < mbudget;
+    for (int sgn = 1; sgn >= -1; sgn -= 2) {
+      if (sgn < 0 && !do_minus) break;
+      const double x = sgn * R;
+      const double y = kap * x + cs;
+      const double X = sqg * y;
+      if (sgn < 0 && X < WX_LO) break;  // below exp(-110) of this chain's F(R)
+      const double E = exp(e0 + a1 * x - a2 * x * x);
+      double Om[NO];
+      {
+        double gp = gp0;
+        if (X >= WX_HI) {
+#pragma unroll
+          for (int i = 0; i < NO; ++i) {
+            Om[i] = (i >= ilo && i <= ihi) ? gp * w_asym_call(F.alpha0 + m0 + i, X) : 0.0;
+            gp *= isq;
+          }
+        } else {
+          const double xs = (X - WX_LO) * WX_INVH;
+          int ix = (int)rint(xs);
+          ix = ix < 0 ? 0 : (ix >= F.nx ? F.nx - 1 : ix);
+          const double Xg = WX_LO + ix * (1.0 / WX_INVH);
+          const double d = X - Xg;
+          const double ef = exp(-d * (2.0 * Xg + d));
+          const double td = 2.0 * d;
+          const double *row = F.table + (int64_t)ix * F.nm - F.m_lo + m0;
+#pragma unroll
+          for (int i = 0; i < NO; ++i) {
+            double v = 0.0;
+            if (i >= ilo && i <= ihi) {
+              const double *r = row + i;
+              double sm = r[KT];
+#pragma unroll
+              for (int k = KT; k >= 1; --k) sm = fma(sm, td * (1.0 / k), r[k - 1]);
+              v = gp * ef * sm;
+            }
+            Om[i] = v;
+            gp *= isq;
+          }
+        }
+      }
+      // Z_k = sum_t c_t d^k/dy^k Omega_{alpha_t}(y), each term's orders picked
+      // by its offset d_t = m_t - m_min through a uniform branch
+      double Z[L + 1];
+#pragma unroll
+      for (int k = 0; k <= L; ++k) Z[k] = 0.0;
+      for (int t = ch.t_begin; t < ch.t_end; ++t) {
+        const double ct = K->terms[t].c;
+        const int mt = K->terms[t].m;
+        const int dt = mt - ch.m_min;
+        const double al = F.alpha0 + mt;
+        const int klow = (F.is_int && mt < L) ? mt : L;
+#pragma unroll
+        for (int dd = 0; dd <= SPAN_C; ++dd) {
+          if (dd == dt) {
+            double ff = 1.0;
+#pragma unroll
+            for (int k = 0; k <= L; ++k) {
+              if (k <= klow) Z[k] += ct * ff * Om[dd + L - k];
+              ff *= (al - k);
+            }
+          }
+        }
+        if (F.is_int && mt < L) {
+          // Omega_mt^(mt+1+j)(y) = mt! e^{-gam y^2} Q_j(y)
+          double fact = 1.0;
+          for (int i = 2; i <= mt; ++i) fact *= i;
+          const double eg = ct * fact * exp(-gam * y * y);
+          double q0 = 1.0, q1 = -2.0 * gam * y;
+#pragma unroll
+          for (int k = 1; k <= L; ++k) {
+            if (k > mt) {
+              const int j = k - mt - 1;
+              double qj;
+              if (j == 0) {
+                qj = q0;
+              } else if (j == 1) {
+                qj = q1;
+              } else {
+                const double q2 = -2.0 * gam * y * q1 - 2.0 * gam * (j - 1) * q0;
+                q0 = q1;
+                q1 = q2;
+                qj = q2;
+              }
+              Z[k] += eg * qj;
+            }
+          }
+        }
+      }
+      // kappa^k Z_k, and E^(j)(x) = E P_j(x): P_{j+1} = (a1 - 2 a2 x) P_j - 2 a2 j P_{j-1}
+      {
+        double kp = 1.0;
+#pragma unroll
+        for (int k = 1; k <= L; ++k) {
+          kp *= kap;
+          Z[k] *= kp;
+        }
+      }
+      double P[L + 1];
+      P[0] = 1.0;
+      const double slope = a1 - 2.0 * a2 * x;
+      if constexpr (L >= 1) P[1] = slope;
+#pragma unroll
+      for (int j = 1; j < L; ++j) P[j + 1] = slope * P[j] - 2.0 * a2 * j * P[j - 1];
+#pragma unroll
+      for (int m = 0; m <= L; ++m) {
+        double G = 0.0, binom = 1.0;
+#pragma unroll
+        for (int j = 0; j <= m; ++j) {
+          G += binom * P[j] * Z[m - j];
+          binom = binom * (m - j) / (j + 1);
+        }
+        G *= E;
+        if (sgn > 0)
+          phi[m] += G;
+        else
+          phi[m] -= (m & 1) ? -G : G;
+      }
+    }
+  }
+  // D^n (phi / R) from the R-jet, as in aux_large
+  double gj[L + 1];
+  double fk = 1.0;
+  double prev = 0.0;
+  const double iR = 1.0 / R;
+#pragma unroll
+  for (int k = 0; k <= L; ++k) {
+    if (k > 0) fk /= k;
+    prev = (phi[k] * fk - prev) * iR;
+    gj[k] = prev;
+  }
+  A[0] = gj[0];
+#pragma unroll
+  for (int n = 1; n <= L; ++n) {
+    double pv = 0.0;
+#pragma unroll
+    for (int k = 0; k <= L - n; ++k) {
+      const double d = (k + 1) * gj[k + 1];
       pv = (d - pv) * iR;
       gj[k] = pv;
     }
@@ -717,8 +908,13 @@ __device__ __forceinline__ int aux_bin(double T, int L, double sw) {
   return 2 + e;
 }
 
-template <bool H>
-__global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__restrict__ K, PairsDev bra,
+// LC >= 0: the compact kernels with L = LC fixed at compile time (H false).
+// Those are held to three waves per SIMD (at most 168 VGPRs): with the
+// unrolled orders in registers the compiler would otherwise take all 256 and
+// leave two waves to hide the latency of the table reads.
+template <bool H, int LC>
+__global__ void __launch_bounds__(F12_NT_AUX) __attribute__((amdgpu_waves_per_eu(LC >= 0 ? 3 : 1)))
+aux_kernel(const KernelDev *__restrict__ K, PairsDev bra,
                                                   PairsDev ket, const int64_t *__restrict__ qb,
                                                   const int64_t *__restrict__ qk,
                                                   const int64_t *__restrict__ qprim, int64_t qa,
@@ -779,6 +975,29 @@ __global__ void __launch_bounds__(F12_NT_AUX) aux_kernel(const KernelDev *__rest
   if (base + me >= np) return;
   const double xi = s_xi[me], u = s_u[me], Np = s_np[me];
   const double T = xi * u;
+  if constexpr (LC >= 0) {
+    double a[LC + 1];
+    if (T < sw) {
+      double as[LTOT_MAX + 1];
+      if (LC <= 5 && T < 2.0)
+        aux_small_f64<false>(K, xi, u, LC, T, as);
+      else
+        aux_small<false>(K, xi, u, LC, T, as);
+#pragma unroll
+      for (int n = 0; n <= LC; ++n) a[n] = as[n];
+    } else {
+      aux_large_c<LC>(K, xi, sqrt(u), minus_budget(T, LC), a);
+    }
+    bool bad = false;
+#pragma unroll
+    for (int n = 0; n <= LC; ++n) {
+      const double v = a[n] * Np;
+      bad |= !isfinite(v);
+      A[n * np + base + me] = v;
+    }
+    if (bad) *fault = 1;
+    return;
+  }
   double a[LTOT_MAX + 1];
   const int Jsr = (H && T >= sw && K->negb) ? short_range_terms(K, xi, T, L) : 0;
   if (T < sw) {
@@ -823,19 +1042,42 @@ int launch_pair_prims(int64_t npp, const int32_t *pp_sa, const int32_t *pp_sb,
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// The compact kernels, one per L, reached through a table of launchers.
+using AuxLaunch = void (*)(dim3, hipStream_t, const KernelDev *, PairsDev, PairsDev, const int64_t *,
+                           const int64_t *, const int64_t *, int64_t, int64_t, int64_t, int64_t, int, double *,
+                           int *);
+template <int LC>
+static void launch_aux_c(dim3 grid, hipStream_t st, const KernelDev *K, PairsDev bra, PairsDev ket,
+                         const int64_t *qb, const int64_t *qk, const int64_t *qprim, int64_t qa, int64_t nqc,
+                         int64_t p0, int64_t np, int L, double *A, int *fw) {
+  hipLaunchKernelGGL((aux_kernel<false, LC>), grid, dim3(F12_NT_AUX), 0, st, K, bra, ket, qb, qk, qprim, qa, nqc,
+                     p0, np, L, A, fw);
+}
+template <int... Ls>
+static const AuxLaunch *aux_table_of(std::integer_sequence<int, Ls...>) {
+  static const AuxLaunch t[] = {&launch_aux_c<Ls>...};
+  return t;
+}
+static const AuxLaunch *compact_aux_table() {
+  return aux_table_of(std::make_integer_sequence<int, LTOT_MAX + 1>{});
+}
+
 int launch_aux(const KernelDev *K, const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
                const int64_t *qk, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
-               int64_t np, int L, double *A, hipStream_t stream, int heavy) {
+               int64_t np, int L, double *A, hipStream_t stream, int variant) {
   if (np <= 0) return 0;
   int *fw = fault_word();
   if (!fw) return -1;
   const int64_t nbk = (np + F12_NT_AUX - 1) / F12_NT_AUX;
-  if (heavy)
-    hipLaunchKernelGGL(aux_kernel<true>, dim3((unsigned)nbk), dim3(F12_NT_AUX), 0, stream, K, bra, ket, qb,
-                       qk, qprim, qa, nqc, p0, np, L, A, fw);
-  else
-    hipLaunchKernelGGL(aux_kernel<false>, dim3((unsigned)nbk), dim3(F12_NT_AUX), 0, stream, K, bra, ket, qb,
-                       qk, qprim, qa, nqc, p0, np, L, A, fw);
+  if (variant == 2 && L >= 0 && L <= LTOT_MAX) {
+    compact_aux_table()[L](dim3((unsigned)nbk), stream, K, bra, ket, qb, qk, qprim, qa, nqc, p0, np, L, A, fw);
+  } else if (variant == 1) {
+    hipLaunchKernelGGL((aux_kernel<true, -1>), dim3((unsigned)nbk), dim3(F12_NT_AUX), 0, stream, K, bra, ket,
+                       qb, qk, qprim, qa, nqc, p0, np, L, A, fw);
+  } else {
+    hipLaunchKernelGGL((aux_kernel<false, -1>), dim3((unsigned)nbk), dim3(F12_NT_AUX), 0, stream, K, bra, ket,
+                       qb, qk, qprim, qa, nqc, p0, np, L, A, fw);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -952,13 +1194,58 @@ __global__ void aux_points_kernel(const KernelDev *__restrict__ K, int64_t n,
   for (int k = 0; k <= L; ++k) A[k * n + t] = a[k] * Np;
 }
 
+// route 0 of a compact kernel: the dispatch of aux_kernel<false, LC>.
+template <int LC>
+__global__ void aux_points_c_kernel(const KernelDev *__restrict__ K, int64_t n, const double *__restrict__ pp,
+                                    const double *__restrict__ qq, const double *__restrict__ RR,
+                                    double *__restrict__ A) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double p = pp[t], q = qq[t], R = RR[t];
+  const double u = R * R;
+  const double xi = p * q / (p + q);
+  const double T = xi * u;
+  const double Np = F12_PI52 / (sqrt(p + q) * p * q);
+  double a[LC + 1];
+  if (T < t_switch_k(K, LC)) {
+    double as[LTOT_MAX + 1];
+    if (LC <= 5 && T < 2.0)
+      aux_small_f64<false>(K, xi, u, LC, T, as);
+    else
+      aux_small<false>(K, xi, u, LC, T, as);
+#pragma unroll
+    for (int k = 0; k <= LC; ++k) a[k] = as[k];
+  } else {
+    aux_large_c<LC>(K, xi, R, minus_budget(T, LC), a);
+  }
+#pragma unroll
+  for (int k = 0; k <= LC; ++k) A[k * n + t] = a[k] * Np;
+}
+
+using AuxPointsLaunch = void (*)(dim3, hipStream_t, const KernelDev *, int64_t, const double *, const double *,
+                                 const double *, double *);
+template <int LC>
+static void launch_points_c(dim3 grid, hipStream_t st, const KernelDev *K, int64_t n, const double *p,
+                            const double *q, const double *R, double *A) {
+  hipLaunchKernelGGL((aux_points_c_kernel<LC>), grid, dim3(128), 0, st, K, n, p, q, R, A);
+}
+template <int... Ls>
+static const AuxPointsLaunch *points_table_of(std::integer_sequence<int, Ls...>) {
+  static const AuxPointsLaunch t[] = {&launch_points_c<Ls>...};
+  return t;
+}
+
 int launch_aux_points(const KernelDev *K, int64_t n, const double *p, const double *q,
-                      const double *R, int L, int route, double *A, hipStream_t stream) {
+                      const double *R, int L, int route, double *A, hipStream_t stream, int variant) {
   if (n <= 0) return 0;
   int nt = 128;
   int64_t nbk = (n + nt - 1) / nt;
-  hipLaunchKernelGGL(aux_points_kernel, dim3((unsigned)nbk), dim3(nt), 0, stream, K, n, p, q, R,
-                     L, route, A);
+  if (route == 0 && variant == 2 && L >= 0 && L <= LTOT_MAX)
+    points_table_of(std::make_integer_sequence<int, LTOT_MAX + 1>{})[L](dim3((unsigned)nbk), stream, K, n, p, q,
+                                                                         R, A);
+  else
+    hipLaunchKernelGGL(aux_points_kernel, dim3((unsigned)nbk), dim3(nt), 0, stream, K, n, p, q, R,
+                       L, route, A);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

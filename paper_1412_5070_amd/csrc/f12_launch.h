@@ -14,7 +14,7 @@ int launch_pair_prims(int64_t npp, const int32_t *pp_sa, const int32_t *pp_sb,
 
 int launch_aux(const KernelDev *K, const PairsDev &bra, const PairsDev &ket, const int64_t *qb,
                const int64_t *qk, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
-               int64_t np, int L, double *A, hipStream_t stream, int heavy);
+               int64_t np, int L, double *A, hipStream_t stream, int variant);
 
 int launch_contract(const PairsDev &bra, const PairsDev &ket, const int64_t *qb, const int64_t *qk,
                     const int64_t *qoff, const int64_t *qprim, int64_t qa, int64_t nqc, int64_t p0,
@@ -29,6 +29,6 @@ int *fault_word();
 
 // Radial derivatives A_n (n = 0..L) for explicit (p, q, R) triples (diagnostic path).
 int launch_aux_points(const KernelDev *K, int64_t n, const double *p, const double *q,
-                      const double *R, int L, int route, double *A, hipStream_t stream);
+                      const double *R, int L, int route, double *A, hipStream_t stream, int variant);
 
 }  // namespace f12
