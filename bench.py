@@ -47,16 +47,16 @@ METRIC = "contracted shell-quartets/s per F12 class at ≤1e-12 rel err; % FP64 
 KERNEL_SOURCES = ["f12_big.h", "f12_common.h", "f12_launch.h", "f12_internal.h", "f12_kernels.hip",
                   "f12_dd.h", "f12_big_unit.hip"]
 TRAFFIC_RECORD = {
-    "sources_sha1": "1440ae3c3fbc90594e905edbd8054ad7f2af2e7c",
+    "sources_sha1": "92de52f1c2f07855cc43c883e2dcf9c15a6c58b8",
     "fetch_scale": 1048576 / 524299.5,
     "write_scale": 1.0,
-    "contraction_bytes_per_launch": 6.43211e+07 + 7.82614e+07,
-    "aux_bytes_per_launch": 7.34461e+08 + 1.38934e+09,
+    "contraction_bytes_per_launch": 6.43047e+07 + 8.13059e+07,
+    "aux_bytes_per_launch": 2.96392e+08 + 5.0318e+08,
     # FP64 flops issued per launch, 64 lanes x (2 SQ_INSTS_VALU_FMA_F64 + SQ_INSTS_VALU_MUL_F64 +
     # SQ_INSTS_VALU_ADD_F64), from one more --pmc pass (profiles/contraction_fp64_counters.md);
     # an upper bound, since lanes masked off are counted too
     "contraction_hw_fp64_flops_per_launch": 3.128e+10,
-    "aux_hw_fp64_flops_per_launch": 1.095e+10,
+    "aux_hw_fp64_flops_per_launch": 8.653e+09,
 }
 
 
