@@ -416,14 +416,18 @@ __device__ __forceinline__ void aux_large_c(const KernelDev *__restrict__ K, dou
           const double ef = exp(-d * (2.0 * Xg + d));
           const double td = 2.0 * d;
           const double *row = F.table + (int64_t)ix * F.nm - F.m_lo + m0;
+          // each table entry of the row is read once (order i takes entries
+          // i .. i + KT, so neighbouring orders share all but one)
+          double seg[NO + KT];
+#pragma unroll
+          for (int j = 0; j < NO + KT; ++j) seg[j] = (j >= ilo && j <= ihi + KT) ? row[j] : 0.0;
 #pragma unroll
           for (int i = 0; i < NO; ++i) {
             double v = 0.0;
             if (i >= ilo && i <= ihi) {
-              const double *r = row + i;
-              double sm = r[KT];
+              double sm = seg[i + KT];
 #pragma unroll
-              for (int k = KT; k >= 1; --k) sm = fma(sm, td * (1.0 / k), r[k - 1]);
+              for (int k = KT; k >= 1; --k) sm = fma(sm, td * (1.0 / k), seg[i + k - 1]);
               v = gp * ef * sm;
             }
             Om[i] = v;
