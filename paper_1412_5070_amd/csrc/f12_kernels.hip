@@ -218,13 +218,22 @@ __device__ void aux_large(const KernelDev *__restrict__ K, double xi, double R, 
           const double ef = exp(-d * (2.0 * Xg + d));
           const double td = 2.0 * d;
           const double *row = F.table + (int64_t)ix * F.nm - F.m_lo;
-          for (int m = mlo; m <= mhi; ++m) {
-            const double *r = row + m;
-            double sm = r[KT];
+          // a window of KT + 1 entries slides along the row: each entry is
+          // read once (order m takes entries m .. m + KT)
+          double w[KT + 1];
 #pragma unroll
-            for (int k = KT; k >= 1; --k) sm = fma(sm, td * (1.0 / k), r[k - 1]);
+          for (int k = 0; k <= KT; ++k) w[k] = row[mlo + k];
+          for (int m = mlo; m <= mhi; ++m) {
+            double sm = w[KT];
+#pragma unroll
+            for (int k = KT; k >= 1; --k) sm = fma(sm, td * (1.0 / k), w[k - 1]);
             Om[m - mlo] = gp * ef * sm;
             gp *= isq;
+            if (m < mhi) {
+#pragma unroll
+              for (int k = 0; k < KT; ++k) w[k] = w[k + 1];
+              w[KT] = row[m + 1 + KT];
+            }
           }
         }
       }
