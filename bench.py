@@ -47,16 +47,16 @@ METRIC = "contracted shell-quartets/s per F12 class at ≤1e-12 rel err; % FP64 
 KERNEL_SOURCES = ["f12_big.h", "f12_common.h", "f12_launch.h", "f12_internal.h", "f12_kernels.hip",
                   "f12_dd.h", "f12_big_unit.hip"]
 TRAFFIC_RECORD = {
-    "sources_sha1": "92de52f1c2f07855cc43c883e2dcf9c15a6c58b8",
+    "sources_sha1": "f86afd91f79959abf087e2a49422980c4fe55839",
     "fetch_scale": 1048576 / 524299.5,
     "write_scale": 1.0,
-    "contraction_bytes_per_launch": 6.43047e+07 + 8.13059e+07,
-    "aux_bytes_per_launch": 2.96392e+08 + 5.0318e+08,
+    "contraction_bytes_per_launch": 6.47169e+07 + 1.37969e+08,
+    "aux_bytes_per_launch": 3.38034e+08 + 5.82893e+08,
     # FP64 flops issued per launch, 64 lanes x (2 SQ_INSTS_VALU_FMA_F64 + SQ_INSTS_VALU_MUL_F64 +
     # SQ_INSTS_VALU_ADD_F64), from one more --pmc pass (profiles/contraction_fp64_counters.md);
     # an upper bound, since lanes masked off are counted too
     "contraction_hw_fp64_flops_per_launch": 3.128e+10,
-    "aux_hw_fp64_flops_per_launch": 8.653e+09,
+    "aux_hw_fp64_flops_per_launch": 8.651e+09,
 }
 
 
