@@ -15,13 +15,16 @@ def block_rel_err(got, ref):
     return float(np.max(np.abs(got - ref)) / scale)
 
 
-def i5_vanishes(la, same_shell):
+def i5_vanishes(la, same_shell, spherical_ket=False):
     """An I5 block vanishes identically when the bra pair is one s or p shell
     taken twice: for l <= 1 the Laplacian of each component x_c e^{-a r^2} is
     x_c h(r) with one h for all components, so
     (lap phi_i) phi_j - phi_i (lap phi_j) = 0 pointwise.  For d and f shells
-    the components are not harmonic and the block does not vanish."""
-    return same_shell and la <= 1
+    the components are not harmonic and the block vanishes only against a
+    spherical ket (two s shells on the bra's centre, spherical_ket): the
+    difference is the divergence of phi_j grad phi_i - phi_i grad phi_j, whose
+    radial part cancels for two components of one shell."""
+    return same_shell and (la <= 1 or spherical_ket)
 
 
 def vanishes_by_parity(quad, shells):

@@ -116,3 +116,30 @@ def test_i5_same_shell_vanishes_over_solid_harmonics():
     S3 = sp.block_to_sph(I3, 2, 2, 1, 0)
     assert np.max(np.abs(I5)) > 1e-3 * np.max(np.abs(I3))
     assert np.max(np.abs(S5)) < 1e-14 * 2.1 * np.max(np.abs(S3)), (np.max(np.abs(S5)), np.max(np.abs(S3)))
+
+
+def test_i5_same_shell_vanishes_for_a_spherical_ket():
+    """With the bra density difference written as a divergence,
+    (lap phi_a) phi_b - phi_a (lap phi_b) = div(phi_b grad phi_a - phi_a grad phi_b),
+    the I5 element is minus the integral of that flux against grad V, V the
+    potential of the ket density.  When the ket is two s shells on the bra's
+    centre, V is spherical about it and only the radial parts of the flux
+    count; for two components P_a g, P_b g of one shell (P homogeneous of
+    degree l, one radial g) those cancel pointwise.  So the oracle's Cartesian
+    I5 block of a d shell taken twice, against s shells on the same centre,
+    vanishes; moved off the centre, the ket gives a block of the size of its
+    terms.  Catches a wrong or one-sided Laplacian term in the oracle's I5."""
+    from oracle import integrals
+    from synth import FACTOR_SETS
+    A = np.array([0.2, -0.1, 0.4])
+    d = {"center": A, "l": 2, "exps": np.array([0.8, 2.3]), "coefs": np.array([0.5, 0.7])}
+    s1 = {"center": A, "l": 0, "exps": np.array([0.6, 1.9]), "coefs": np.array([0.3, 0.8])}
+    s2 = {"center": A, "l": 0, "exps": np.array([1.4]), "coefs": np.array([1.0])}
+    P1 = FACTOR_SETS["P1"]
+    I5 = np.asarray(integrals.contracted(5, d, d, s1, s2, P1, P1), dtype=float)
+    I3 = np.asarray(integrals.contracted(3, d, d, s1, s2, P1, P1), dtype=float)
+    assert np.max(np.abs(I5)) < 1e-14 * 2.3 * np.max(np.abs(I3)), (np.max(np.abs(I5)), np.max(np.abs(I3)))
+    s2_off = dict(s2, center=A + np.array([0.0, 0.9, -0.4]))
+    J5 = np.asarray(integrals.contracted(5, d, d, s1, s2_off, P1, P1), dtype=float)
+    J3 = np.asarray(integrals.contracted(3, d, d, s1, s2_off, P1, P1), dtype=float)
+    assert np.max(np.abs(J5)) > 1e-3 * np.max(np.abs(J3))
