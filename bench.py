@@ -47,7 +47,7 @@ METRIC = "contracted shell-quartets/s per F12 class at ≤1e-12 rel err; % FP64 
 KERNEL_SOURCES = ["f12_big.h", "f12_common.h", "f12_launch.h", "f12_internal.h", "f12_kernels.hip",
                   "f12_dd.h", "f12_big_unit.hip"]
 TRAFFIC_RECORD = {
-    "sources_sha1": "f86afd91f79959abf087e2a49422980c4fe55839",
+    "sources_sha1": "f853387ce201a7e7018054ab771dbd2dbc23c7cb",
     "fetch_scale": 1048576 / 524299.5,
     "write_scale": 1.0,
     "contraction_bytes_per_launch": 6.47169e+07 + 1.37969e+08,

@@ -922,9 +922,10 @@ __device__ __forceinline__ int aux_bin(double T, int L, double sw) {
 }
 
 // LC >= 0: the compact kernels with L = LC fixed at compile time (H false).
-// Those are held to three waves per SIMD (at most 168 VGPRs): with the
-// unrolled orders in registers the compiler would otherwise take all 256 and
-// leave two waves to hide the latency of the table reads.
+// Those are held to at most 168 VGPRs (the register budget of three waves per
+// SIMD).  A 512-thread work-group still runs two waves per SIMD either way;
+// the cap is kept because it was measured faster: with all 256 registers the
+// launches take 1.5-1.9x as long, capped at 128 (spilling more) 1.1x.
 template <bool H, int LC>
 __global__ void __launch_bounds__(F12_NT_AUX) __attribute__((amdgpu_waves_per_eu(LC >= 0 ? 3 : 1)))
 aux_kernel(const KernelDev *__restrict__ K, PairsDev bra,
