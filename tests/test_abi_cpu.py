@@ -53,6 +53,16 @@ def test_eval_sets_validation_before_device():
     assert lib.f12_eval_sets(None, arr, 0, 0, 0, None, 0, None) == -1
 
 
+def test_digest_validation_before_device():
+    """f12_digest rejects a null list or a null digest pointer before any
+    device work."""
+    from paper_1412_5070_amd import f12int
+    lib = f12int._lib
+    dummy = ctypes.c_uint64(0)
+    assert lib.f12_digest(None, 0, 0, None, ctypes.cast(ctypes.pointer(dummy), ctypes.c_void_p), None) == -1
+    assert lib.f12_digest(None, 0, 1, None, None, None) == -1
+
+
 def test_basis_validation():
     from paper_1412_5070_amd import f12int
     ok = ([[0, 0, 0]], [[1, 2, 0, 0]], [1.0, 0.5], [0.3, 0.7])
